@@ -1,0 +1,203 @@
+"""Benchmark: UCCSD energy evaluations per second on one MI355X.
+
+Workload (default): 16 qubits (8 orbitals, 8 electrons), seeded synthetic
+integrals and UCCSD amplitudes, MPS bond dimension D = 64, complex128 (FP64)
+throughout, one energy evaluation per step: Hartree-Fock product state ->
+55,424 fused nearest-neighbour gates (contraction + FP64 SVD + truncation +
+update each) -> identity environments -> 5,792 Pauli-string transfer sweeps
+-> compensated sum.
+
+Prints one JSON line.  ``roofline`` is for the dominant kernel (the gate
+kernel): algorithmic FLOPs of the gate updates at the realised bond
+dimensions (counted on the device) over the HIP-event time of its launches
+on the library's stream, against the FP64 vector peak.  ``cpu_baseline`` is
+the CPU oracle (numpy + LAPACK) timed on this host over a bounded prefix of
+the same gate sequence plus a sample of Pauli sweeps, extrapolated to one
+evaluation by algorithmic FLOPs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from workloads import CONFIGS  # noqa: E402
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD_TEXT = {
+    "q8_d16": "8 qubits (4 orbitals, 4 electrons), D=16 (full), complex128, single energy evaluation",
+    "q16_d64": "16 qubits (8 orbitals, 8 electrons), D=64, complex128, single energy evaluation",
+    "q24_d128": "24 qubits (12 orbitals, 12 electrons), D=128, complex128, single energy evaluation",
+    "q24_d256": "24 qubits (12 orbitals, 12 electrons), D=256, complex128, single energy evaluation",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gate_flops(chil, chim, chir, keep):
+    m, n = 2 * chil, 2 * chir
+    mm, nm = max(m, n), min(m, n)
+    return (32.0 * chil * chim * chir + 128.0 * chil * chir + 4.0 * (4.0 * mm * nm * nm + 8.0 * nm ** 3)
+            + 8.0 * m * n * keep)
+
+
+def cpu_baseline(cfg, gpu_flops_per_eval, budget_s):
+    """Time the oracle on a prefix of the gate list (budget_s of work) and a
+    sample of Pauli sweeps; extrapolate to one evaluation."""
+    import threadpoolctl
+
+    from oracle import fermion, mps as om, uccsd
+
+    cores = len(os.sched_getaffinity(0))
+    I = cfg.integrals()
+    th = cfg.theta()
+    n = 2 * cfg.n_orb
+    with threadpoolctl.threadpool_limits(cores):
+        c_id, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri))
+        rots, gates = uccsd.compile_fused(n, cfg.n_elec)
+        phis = uccsd.rotation_angles(rots, th)
+        m = om.MPS(uccsd.hf_occupation(n, cfg.n_elec), cfg.max_bond)
+        t0 = time.perf_counter()
+        done, fl = 0, 0.0
+        for g in gates:
+            chil, chim, chir = m.B[g.site].shape[0], m.B[g.site].shape[2], m.B[g.site + 1].shape[2]
+            m.apply_gate(g.site, g.matrix(phis))
+            fl += gate_flops(chil, chim, chir, m.chi(g.site))
+            done += 1
+            if time.perf_counter() - t0 > budget_s * 0.85:
+                break
+        t_gates = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        pick = rng.choice(len(terms), size=min(len(terms), 64), replace=False)
+        t1 = time.perf_counter()
+        om.pauli_expectations(m, [terms[i] for i in pick])
+        t_sweep = (time.perf_counter() - t1) * len(terms) / len(pick)
+    t_eval = t_gates * (gpu_flops_per_eval / fl) + t_sweep
+    return {
+        "value": 1.0 / t_eval,
+        "unit": "evals/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"first {done} of {len(gates)} gates ({t_gates:.1f} s, {fl:.3e} algorithmic FLOPs) "
+                   f"extrapolated by algorithmic FLOPs to {gpu_flops_per_eval:.3e}, plus {len(pick)} of "
+                   f"{len(terms)} Pauli sweeps on the prefix state scaled to all strings; numpy/LAPACK "
+                   f"with {cores} BLAS threads"),
+        "seconds_per_eval": t_eval,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="q16_d64", choices=sorted(CONFIGS))
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the energy path has no multi-GPU mode in this build "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2207_03711_amd import q2c
+
+    cfg = CONFIGS[args.workload]
+    I = cfg.integrals()
+    th = cfg.theta()
+    ctx = q2c.Context(0)
+    prob = q2c.Problem(ctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+    log("problem", prob.info)
+    for w in range(args.warmup):
+        e, st = prob.energy(th, cfg.max_bond)
+        log(f"warmup {w}: E={e:.12f} {st['seconds']:.2f}s gate_ms={st['gate_ms']:.1f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = None
+    energies = []
+    for k in range(args.steps):
+        e, st = prob.energy(th, cfg.max_bond)
+        energies.append(e)
+        log(f"step {k}: E={e:.12f} {st['seconds']:.2f}s gate_ms={st['gate_ms']:.1f}")
+        if agg is None:
+            agg = {key: 0.0 for key in ("gate_flops", "gate_ms", "env_ms", "pauli_ms", "reduce_ms",
+                                        "gate_launches", "jacobi_sweeps")}
+        for key in agg:
+            agg[key] += st[key]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    K = args.steps
+    value = K / elapsed
+    flops_eval = agg["gate_flops"] / K
+    launches = agg["gate_launches"]
+    flops_per_launch = agg["gate_flops"] / launches
+    ms_per_launch = agg["gate_ms"] / launches
+    achieved = flops_per_launch / (ms_per_launch * 1e-3) / 1e12
+    out = {
+        "metric": "uccsd_energy_evals_per_s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, args.workload)}",
+            "n_qubits": prob.info["n_qubits"],
+            "max_bond": cfg.max_bond,
+            "n_gates": prob.info["n_gates"],
+            "n_strings": prob.info["n_strings"],
+            "n_params": prob.info["n_params"],
+            "int_seed": cfg.int_seed,
+            "theta_seed": cfg.theta_seed,
+        },
+        "energy": energies[-1],
+        "phase_ms_per_eval": {k: agg[k] / K for k in ("gate_ms", "env_ms", "pauli_ms", "reduce_ms")},
+        "stats": {"max_chi": st["max_chi"], "discarded_weight_sum": st["discarded_weight_sum"],
+                  "max_abs_imag": st["max_abs_imag"], "jacobi_sweeps_per_gate":
+                  agg["jacobi_sweeps"] / K / prob.info["n_gates"], "max_sweeps_used": st["max_sweeps_used"]},
+        "roofline": {
+            "kernel": "k_gates",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops_per_launch,
+            "ms_per_launch": ms_per_launch,
+            "launches_per_eval": launches / K,
+        },
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, flops_eval, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

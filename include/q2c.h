@@ -1,0 +1,214 @@
+/*
+ * q2c.h -- C ABI of the MI355X MPS-VQE energy library (libq2c.so).
+ *
+ * The library evaluates the UCCSD energy E(theta) = <psi(theta)|H|psi(theta)>
+ * of a Jordan-Wigner Pauli-string Hamiltonian on a matrix product state, the
+ * hot path of the MPS-VQE simulator in "Large-Scale Simulation of Quantum
+ * Computational Chemistry on a New Sunway Supercomputer" (Sec. II-A, III-A,
+ * III-D).  Everything that scales with the state runs in HIP kernels on one
+ * gfx950 GPU; the host only validates arguments, compiles the problem once
+ * and launches.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Qubits / sites / spin-orbitals: qubit n = MPS site n = spin-orbital n,
+ *   interleaved spins (2p = p-alpha, 2p+1 = p-beta).  |1> = occupied.
+ * Two-qubit gates act on (site, site+1); the 4x4 matrix is row-major with
+ *   basis index 2*i_site + i_{site+1}, complex values stored as interleaved
+ *   (re, im) doubles: 32 doubles per gate.
+ * Pauli strings: bit b of word w of a mask refers to qubit 64*w + b.
+ *   A qubit carries X if only its x bit is set, Z if only its z bit is set,
+ *   Y if both are set.  n_words = ceil(n_qubits / 64).
+ * Ownership: every pointer argument is a HOST pointer owned by the caller and
+ *   only read (or, for outputs, written) during the call; the library copies
+ *   what it keeps.  Device memory belongs to the library.  Handles are opaque
+ *   and freed by the matching *_destroy.
+ * Synchronisation: a call returns after its device work has finished and its
+ *   host outputs are valid.  Calls on one context must not overlap (one host
+ *   thread per context at a time); different contexts are independent.
+ * Errors: every entry point returns Q2C_OK (0) or a negative Q2C_ERR_* code.
+ *   On error no output is written and q2c_last_error() returns a message
+ *   (thread-local, valid until the next call on that thread).  No C++
+ *   exception crosses this boundary.
+ */
+#ifndef Q2C_H
+#define Q2C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  Q2C_OK = 0,
+  Q2C_ERR_ARG = -1,     /* bad size, index, NULL, NaN/Inf input, theta length mismatch */
+  Q2C_ERR_OOM = -2,     /* device allocation or the context's HBM budget failed          */
+  Q2C_ERR_DEVICE = -3,  /* a HIP call failed, or no usable gfx950 device                   */
+  Q2C_ERR_NOCONV = -4,  /* Jacobi SVD reached max_sweeps without converging               */
+  Q2C_ERR_NUMERIC = -5, /* non-finite values appeared on the device                         */
+  Q2C_ERR_BUSY = -6     /* the handle is in use by an unfinished operation                  */
+};
+
+enum { Q2C_FP64 = 0, Q2C_MIXED = 1 };
+
+typedef struct q2c_ctx q2c_ctx;
+typedef struct mps_state mps_state;
+typedef struct vqe_problem vqe_problem;
+
+/* Options of a context.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+  int max_sweeps;           /* Jacobi sweep limit per SVD (0 -> 60)                      */
+  double sv_cutoff_rel;     /* keep s_k > sv_cutoff_rel * s_1 (0 -> 1e-12)               */
+  double svd_tol;           /* rotate a row pair while |<r_p,r_q>| > svd_tol*|r_p||r_q|
+                               (0 -> 1e-15)                                               */
+  int slots;                /* max circuits resident at once in batched calls (0 -> 256)  */
+  size_t hbm_budget_bytes;  /* device memory the context may hold (0 -> 64 GiB)           */
+} q2c_opts;
+
+/* Statistics of the last state evolution (all over the gates applied). */
+typedef struct {
+  double discarded_weight_sum; /* sum over gates of sum_{k>chi'} s_k^2 / sum_k s_k^2     */
+  double max_discarded;        /* largest single-gate discarded weight                    */
+  double max_abs_imag;         /* max |Im <P>| over the strings evaluated                 */
+  double norm;                 /* <psi|psi> of the stored MPS before division            */
+  int max_chi;                 /* largest bond dimension reached                          */
+  int max_sweeps_used;         /* most Jacobi sweeps any SVD needed                       */
+  double seconds;              /* wall time of the call                                   */
+  /* Device-side accounting, summed over every circuit of the call:                         */
+  double gate_flops;           /* algorithmic FLOPs of the gate updates at the realised
+                                  bond dimensions: per gate 32 cl cm cr + 128 cl cr
+                                  (contraction), 4 (4 m n^2 + 8 n^3) with m >= n the sides
+                                  of the 2cl x 2cr matrix (SVD, singular values and right
+                                  vectors), 8 (2cl)(2cr) chi' (update)                     */
+  double jacobi_sweeps;        /* Jacobi sweeps executed                                  */
+  double gate_ms;              /* HIP-event time of the gate-kernel launches              */
+  double env_ms;               /* HIP-event time of the environment kernel                */
+  double pauli_ms;             /* HIP-event time of the Pauli-sweep kernel                */
+  double reduce_ms;            /* HIP-event time of the energy reduction                  */
+  int gate_launches;           /* gate-kernel launches                                    */
+  int n_circuits;              /* circuits (MPS evolutions) run                           */
+} q2c_stats;
+
+/* Context: one device, one HIP stream.
+ *   device      HIP device ordinal.
+ *   hip_stream  hipStream_t to launch on, or NULL for a stream the context
+ *               creates (default priority).  A caller-provided stream stays
+ *               owned by the caller.
+ *   opts        may be NULL for defaults.
+ * Returns Q2C_ERR_DEVICE if the device is absent or is not gfx950. */
+int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx** out);
+int q2c_ctx_destroy(q2c_ctx* ctx);
+
+/* Matrix product state in a product state (Eq. 6 with every bond of
+ * dimension 1, e.g. the Hartree-Fock reference of Sec. III-D prepared by X
+ * gates).  Bond n (between sites n and n+1) may grow to
+ * min(2^(n+1), 2^(N-n-1), max_bond).
+ *   n_qubits  2..64.
+ *   max_bond  1..256 (D).
+ *   precision Q2C_FP64 (complex128 throughout) or Q2C_MIXED.
+ *   occ       n_qubits bytes, 0 or 1 (site n starts in |occ[n]>). */
+int mps_create(q2c_ctx* ctx, int n_qubits, int max_bond, int precision,
+               const uint8_t* occ, mps_state** out);
+int mps_destroy(mps_state* s);
+
+/* Apply one two-qubit gate to sites (site, site+1) and restore the MPS form
+ * (Sec. III-A, Eq. 7-10): contract the gate with the two site tensors, scale
+ * by the left bond's Schmidt values, take the SVD in FP64, keep the
+ * min(D, #{s_k > cutoff * s_1}) largest Schmidt values (renormalised), set
+ * site+1 to the kept right singular vectors and site to M W / ||S_kept||.
+ *   site   0..n_qubits-2.
+ *   gate   32 doubles (4x4 complex, row-major, interleaved re/im); need not
+ *          be unitary, but must be finite.
+ *   discarded_weight  nullable; receives sum_{k>chi'} s_k^2 / sum_k s_k^2. */
+int mps_apply_gate(mps_state* s, int site, const double* gate, double* discarded_weight);
+
+/* Expectation values <psi|P|psi> / <psi|psi> of Hermitian Pauli strings by
+ * exact transfer-matrix contraction of the stored MPS (Eq. 2, Eq. 11).
+ *   x_masks, z_masks  n_strings * n_words uint64 each, string-major.
+ *   out_re            n_strings doubles.
+ *   out_im            nullable; n_strings doubles (zero up to rounding). */
+int mps_expect_pauli_batch(mps_state* s, int n_strings, int n_words,
+                           const uint64_t* x_masks, const uint64_t* z_masks,
+                           double* out_re, double* out_im);
+
+/* Copy the site tensors and Schmidt values to the host (debugging, checks).
+ *   chi_out   n_qubits+1 ints: chi_out[0] = 1, chi_out[n+1] = right bond of
+ *             site n, chi_out[N] = 1.
+ *   tensors   nullable; receives site after site, each chi_l x 2 x chi_r
+ *             complex (interleaved doubles) row-major; size from chi_out.
+ *   lambdas   nullable; receives bond after bond (n_qubits-1 bonds). */
+int mps_export(mps_state* s, int* chi_out, double* tensors, double* lambdas);
+int mps_get_stats(mps_state* s, q2c_stats* stats);
+
+/* Problem: integrals (Eq. 1) -> Jordan-Wigner Pauli strings (Eq. 2) and the
+ * UCCSD ansatz (Eq. 3-4) as a first-order Trotter product of Pauli
+ * rotations, compiled to nearest-neighbour two-qubit gates with the
+ * single-qubit gates fused in (Sec. III-A, III-D).
+ *   ctx     may be NULL: the problem is then compiled on the host only and
+ *           can be inspected with vqe_problem_info / _paulis / _gates, but
+ *           not evaluated.
+ *   n_orb   1..32 spatial orbitals (2*n_orb qubits).
+ *   n_elec  even, 0..2*n_orb; Hartree-Fock occupies spin-orbitals 0..n_elec-1.
+ *   h1      n_orb^2 doubles, symmetric.
+ *   eri     n_orb^4 doubles, chemist notation (pq|rs), row-major [p][q][r][s].
+ *   e_const constant added to the energy. */
+int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1,
+                       const double* eri, double e_const, vqe_problem** out);
+int vqe_problem_destroy(vqe_problem* p);
+
+/* Sizes of a compiled problem (any pointer may be NULL). */
+int vqe_problem_info(const vqe_problem* p, int* n_qubits, int* n_params, int* n_strings,
+                     int* n_rotations, int* n_gates, double* identity_coeff);
+/* Pauli strings in the order they are summed (ascending (x, z)), excluding
+ * the identity; x, z: n_strings * n_words each; coeff: n_strings. */
+int vqe_problem_paulis(const vqe_problem* p, uint64_t* x, uint64_t* z, double* coeff);
+/* Rotations: x, z masks, coefficient c (phi = -2 c theta[param]), param. */
+int vqe_problem_rotations(const vqe_problem* p, uint64_t* x, uint64_t* z, double* c,
+                          int* param);
+/* Gates in application order: site, rotation index (-1 if constant), and
+ * pre/post 4x4 complex (32 doubles each).  A constant gate is `pre` (post is
+ * the identity); an angle gate is post * kron(I, RZ(phi)) * pre. */
+int vqe_problem_gates(const vqe_problem* p, int* site, int* rot, double* pre, double* post);
+
+/* E(theta) = E_const + c_I + sum_P c_P <P>, from the Hartree-Fock product
+ * state through every compiled gate at bond dimension max_bond, then the
+ * Pauli sum (FP64, compensated, fixed order).
+ *   theta  n_theta doubles; n_theta must equal the problem's n_params.
+ *   stats  nullable. */
+int vqe_energy(vqe_problem* p, const double* theta, int n_theta, int max_bond, int precision,
+               double* energy, q2c_stats* stats);
+
+/* Energies of n_batch independent parameter vectors (theta is n_batch x
+ * n_theta, row-major), run as concurrent circuits on the device.
+ *   energies  n_batch doubles. */
+int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_theta,
+                     int max_bond, int precision, double* energies, q2c_stats* stats);
+
+/* Gradient by the two-term parameter shift of every rotation angle:
+ * dE/dtheta_k = sum_{m in k} (-2 c_m) (E(phi_m + pi/2) - E(phi_m - pi/2)) / 2.
+ * All shifted circuits (2 per rotation) and the unshifted one run as a batch.
+ *   grad    n_theta doubles.
+ *   energy  nullable; E(theta). */
+int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int max_bond,
+                        int precision, double* grad, double* energy, q2c_stats* stats);
+
+/* Shifted-circuit energies for a chosen subset of rotations (for sampling
+ * and tests): for each listed rotation m, e_plus[i] = E(phi_m + pi/2) and
+ * e_minus[i] = E(phi_m - pi/2). */
+int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const int* rot_idx,
+                       int n_rot, int max_bond, int precision, double* e_plus, double* e_minus,
+                       q2c_stats* stats);
+
+/* Thread-local message for the last non-OK return on this thread. */
+const char* q2c_last_error(void);
+
+/* Library version string. */
+const char* q2c_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Q2C_H */

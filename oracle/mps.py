@@ -31,10 +31,28 @@ from .statevector import neumaier_sum
 SV_CUTOFF_REL = 1e-12
 
 
+def _svd_gesdd(mat):
+    return np.linalg.svd(mat, full_matrices=False)
+
+
+def _svd_gesvd(mat):
+    import scipy.linalg
+
+    return scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesvd")
+
+
+SVD_DRIVERS = {"gesdd": _svd_gesdd, "gesvd": _svd_gesvd}
+
+
 class MPS:
-    def __init__(self, occ, max_bond: int):
+    """``svd`` selects the LAPACK driver (divide-and-conquer ``gesdd`` or
+    QR-iteration ``gesvd``); both are backward-stable, and comparing them
+    measures how far rounding alone moves a truncated trajectory."""
+
+    def __init__(self, occ, max_bond: int, svd: str = "gesdd"):
         self.n = len(occ)
         self.D = max_bond
+        self._svd = SVD_DRIVERS[svd]
         self.B = []
         for o in occ:
             t = np.zeros((1, 2, 1), dtype=complex)
@@ -60,7 +78,7 @@ class MPS:
         M = np.einsum("ijkl,aklc->aijc", O4, theta)
         Mp = self.lam_left(n)[:, None, None, None] * M
         mat = Mp.reshape(2 * chil, 2 * chir)
-        _, S, Wh = np.linalg.svd(mat, full_matrices=False)
+        _, S, Wh = self._svd(mat)
         nz = int(np.count_nonzero(S > SV_CUTOFF_REL * S[0]))
         keep = min(self.D, nz)
         if keep < nz:
@@ -157,8 +175,8 @@ def energy(mps: MPS, c_id: float, terms) -> tuple[float, float]:
     return neumaier_sum(vals + [c_id]), float(np.max(np.abs(ev.imag))) if len(ev) else 0.0
 
 
-def run_circuit(n: int, occ, gates, phis, max_bond: int, progress=None) -> MPS:
-    mps = MPS(occ, max_bond)
+def run_circuit(n: int, occ, gates, phis, max_bond: int, progress=None, svd: str = "gesdd") -> MPS:
+    mps = MPS(occ, max_bond, svd)
     for g_i, g in enumerate(gates):
         mps.apply_gate(g.site, g.matrix(phis))
         if progress and g_i % 5000 == 0:

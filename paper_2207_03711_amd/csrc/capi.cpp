@@ -1,0 +1,859 @@
+// C ABI of libq2c: argument checking, device memory, launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/q2c.h"
+#include "compile.hpp"
+#include "engine.hpp"
+
+using q2c::cplx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct DeviceError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct OomError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct StatusError : std::runtime_error {
+  int code;
+  StatusError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw OomError(std::string(what) + ": " + hipGetErrorString(e));
+    throw DeviceError(std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    return Q2C_OK;
+  } catch (const ArgError& e) {
+    g_last_error = e.what();
+    return Q2C_ERR_ARG;
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
+    return Q2C_ERR_ARG;
+  } catch (const OomError& e) {
+    g_last_error = e.what();
+    return Q2C_ERR_OOM;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return Q2C_ERR_OOM;
+  } catch (const StatusError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const DeviceError& e) {
+    g_last_error = e.what();
+    return Q2C_ERR_DEVICE;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return Q2C_ERR_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return Q2C_ERR_DEVICE;
+  }
+}
+
+void require(bool ok, const char* msg) {
+  if (!ok) throw ArgError(msg);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context --
+
+struct q2c_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  q2c_opts opts{};
+  size_t bytes_in_use = 0;
+
+  void activate() const { hip_check(hipSetDevice(device), "hipSetDevice"); }
+
+  void* dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (bytes_in_use + bytes > opts.hbm_budget_bytes)
+      throw OomError("context HBM budget exceeded (" + std::to_string(bytes_in_use + bytes) + " > " +
+                     std::to_string(opts.hbm_budget_bytes) + " bytes)");
+    void* p = nullptr;
+    hip_check(hipMalloc(&p, bytes), "hipMalloc");
+    bytes_in_use += bytes;
+    return p;
+  }
+  void dfree(void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    bytes_in_use -= std::min(bytes_in_use, bytes == 0 ? size_t(16) : bytes);
+  }
+};
+
+namespace {
+
+// RAII device buffer charged to a context.
+struct DBuf {
+  q2c_ctx* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(q2c_ctx* c, size_t n) : ctx(c), p(c->dalloc(n)), bytes(n) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : ctx(o.ctx), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    release();
+    ctx = o.ctx;
+    p = o.p;
+    bytes = o.bytes;
+    o.p = nullptr;
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p && ctx) ctx->dfree(p, bytes);
+    p = nullptr;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+long bond_cap(int N, int b, int D) {
+  // capacity of bond b (between sites b and b+1), b in -1..N-1
+  if (b < 0 || b >= N - 1) return 1;
+  long left = (b + 1 >= 40) ? (1L << 40) : (1L << (b + 1));
+  long right = (N - b - 1 >= 40) ? (1L << 40) : (1L << (N - b - 1));
+  return std::min<long>(std::min(left, right), D);
+}
+
+// Owns the device arrays of a batch of MPS slots.
+struct Batch {
+  q2c::DevBatch d;
+  int cm = 1;  // largest bond cap
+  std::vector<DBuf> bufs;
+
+  Batch(q2c_ctx* ctx, int N, int D, int slots) {
+    auto& b = d;
+    b.n_qubits = N;
+    b.max_bond = D;
+    b.n_slots = slots;
+    for (int i = 0; i <= N; ++i) b.cap[i] = int(bond_cap(N, i - 1, D));
+    cm = 1;
+    for (int i = 0; i <= N; ++i) cm = std::max(cm, b.cap[i]);
+    b.ws = 2 * cm;
+    long off = 0;
+    for (int n = 0; n < N; ++n) {
+      b.site_off[n] = off;
+      off += long(b.cap[n]) * 2 * b.cap[n + 1];
+    }
+    b.site_off[N] = off;
+    b.site_stride = (off + 31) & ~31L;
+    off = 0;
+    for (int bb = 0; bb < N - 1; ++bb) {
+      b.lam_off[bb] = off;
+      off += b.cap[bb + 1];
+    }
+    b.lam_off[N - 1] = off;
+    b.lam_stride = std::max<long>(32, (off + 31) & ~31L);
+    off = 0;
+    for (int k = 0; k <= N; ++k) {
+      b.env_off[k] = off;
+      off += long(b.cap[k]) * b.cap[k];
+    }
+    b.env_off[N + 1] = off;
+    b.env_stride = (off + 31) & ~31L;
+    b.ws_stride = long(b.ws) * b.ws;
+    auto alloc = [&](size_t bytes) -> void* {
+      bufs.emplace_back(ctx, bytes);
+      return bufs.back().p;
+    };
+    const size_t S = size_t(slots);
+    b.sites = static_cast<double2*>(alloc(S * b.site_stride * sizeof(double2)));
+    b.lam = static_cast<double*>(alloc(S * b.lam_stride * sizeof(double)));
+    b.chi = static_cast<int*>(alloc(S * (N + 1) * sizeof(int)));
+    b.wsM = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
+    b.wsA = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
+    b.wsH = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
+    b.wsW = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
+    b.wsS = static_cast<double*>(alloc(S * 2 * b.ws * sizeof(double)));
+    b.wsP = static_cast<int*>(alloc(S * b.ws * sizeof(int)));
+    b.envL = static_cast<double2*>(alloc(S * b.env_stride * sizeof(double2)));
+    b.envR = static_cast<double2*>(alloc(S * b.env_stride * sizeof(double2)));
+    b.stats = static_cast<double*>(alloc(S * q2c::kNStats * sizeof(double)));
+    b.flags = static_cast<int*>(alloc(S * sizeof(int)));
+    b.phi = nullptr;
+  }
+};
+
+q2c::SvdParams svd_params(const q2c_ctx* ctx) {
+  q2c::SvdParams sp;
+  sp.max_sweeps = ctx->opts.max_sweeps;
+  sp.tol = ctx->opts.svd_tol;
+  sp.cutoff_rel = ctx->opts.sv_cutoff_rel;
+  return sp;
+}
+
+// HIP-event times and launch counts of the device phases of a call.
+struct PhaseTimes {
+  double gate_ms = 0, env_ms = 0, pauli_ms = 0, reduce_ms = 0;
+  int gate_launches = 0, circuits = 0;
+};
+
+struct Events {
+  hipEvent_t e[5] = {};
+  Events() {
+    for (auto& x : e) hip_check(hipEventCreate(&x), "hipEventCreate");
+  }
+  ~Events() {
+    for (auto& x : e) (void)hipEventDestroy(x);
+  }
+  double ms(int a, int b) const {
+    float t = 0.f;
+    hip_check(hipEventElapsedTime(&t, e[a], e[b]), "hipEventElapsedTime");
+    return double(t);
+  }
+};
+
+void fill_stats(q2c_stats* out, const std::vector<double>& st, int slots, double seconds,
+                const PhaseTimes& pt = PhaseTimes()) {
+  if (!out) return;
+  q2c_stats s{};
+  for (int i = 0; i < slots; ++i) {
+    const double* p = &st[size_t(i) * q2c::kNStats];
+    s.discarded_weight_sum = std::max(s.discarded_weight_sum, p[q2c::kStatDisc]);
+    s.max_discarded = std::max(s.max_discarded, p[q2c::kStatMaxDisc]);
+    s.max_chi = std::max(s.max_chi, int(p[q2c::kStatMaxChi]));
+    s.max_sweeps_used = std::max(s.max_sweeps_used, int(p[q2c::kStatSweeps]));
+    s.max_abs_imag = std::max(s.max_abs_imag, p[q2c::kStatMaxImag]);
+    s.gate_flops += p[q2c::kStatFlops];
+    s.jacobi_sweeps += p[q2c::kStatSweepSum];
+    if (i == 0) s.norm = p[q2c::kStatNorm];
+  }
+  s.seconds = seconds;
+  s.gate_ms = pt.gate_ms;
+  s.env_ms = pt.env_ms;
+  s.pauli_ms = pt.pauli_ms;
+  s.reduce_ms = pt.reduce_ms;
+  s.gate_launches = pt.gate_launches;
+  s.n_circuits = pt.circuits;
+  *out = s;
+}
+
+void check_flags(const std::vector<int>& flags) {
+  int f = 0;
+  for (int v : flags) f |= v;
+  if (f & q2c::kFlagNumeric) throw StatusError(Q2C_ERR_NUMERIC, "non-finite or zero Schmidt values on the device");
+  if (f & q2c::kFlagNoConv) throw StatusError(Q2C_ERR_NOCONV, "Jacobi SVD reached max_sweeps without converging");
+}
+
+constexpr int kGateChunk = 8192;
+
+}  // namespace
+
+// ------------------------------------------------------------------- handles --
+
+struct mps_state {
+  q2c_ctx* ctx = nullptr;
+  int n = 0, D = 0, precision = 0;
+  std::unique_ptr<Batch> batch;
+  DBuf occ, gsite, grot, gmat, scratch, ev_re, ev_im, sx, sz;
+  int scratch_wg = 0;
+};
+
+struct vqe_problem {
+  q2c_ctx* ctx = nullptr;
+  q2c::Problem host;
+  q2c::DevProblem dev;
+  DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, occ;
+  std::map<std::pair<int, int>, std::unique_ptr<Batch>> batches;  // (D, slots)
+  DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi;
+  size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
+         phi_cap = 0;
+};
+
+namespace {
+
+void ensure(q2c_ctx* ctx, DBuf& buf, size_t& cap, size_t bytes) {
+  if (cap >= bytes && buf.p) return;
+  buf = DBuf(ctx, bytes);
+  cap = bytes;
+}
+
+// Runs n_slots circuits of problem p with theta (n_slots x n_params) and
+// optional per-slot shifts; writes per-slot energies.
+void run_circuits(vqe_problem* p, int D, const double* theta, int n_slots, const int* shift_rot,
+                  const double* shift_val, double* energies, std::vector<double>& stats_out, PhaseTimes& pt) {
+  Events ev;
+  q2c_ctx* ctx = p->ctx;
+  ctx->activate();
+  hipStream_t st = ctx->stream;
+  const auto& H = p->host;
+  const int np = H.n_params;
+  auto key = std::make_pair(D, n_slots);
+  if (!p->batches.count(key)) p->batches[key] = std::make_unique<Batch>(ctx, H.n_qubits, D, n_slots);
+  Batch& B = *p->batches[key];
+  q2c::DevBatch db = B.d;
+
+  ensure(ctx, p->theta, p->theta_cap, sizeof(double) * std::max(1, n_slots * np));
+  if (np) hip_check(hipMemcpyAsync(p->theta.p, theta, sizeof(double) * n_slots * np, hipMemcpyHostToDevice, st), "copy theta");
+  const int* d_shift_rot = nullptr;
+  const double* d_shift_val = nullptr;
+  if (shift_rot) {
+    ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * n_slots);
+    ensure(ctx, p->shift_val, p->sval_cap, sizeof(double) * n_slots);
+    hip_check(hipMemcpyAsync(p->shift_rot.p, shift_rot, sizeof(int) * n_slots, hipMemcpyHostToDevice, st), "copy shifts");
+    hip_check(hipMemcpyAsync(p->shift_val.p, shift_val, sizeof(double) * n_slots, hipMemcpyHostToDevice, st), "copy shifts");
+    d_shift_rot = p->shift_rot.as<int>();
+    d_shift_val = p->shift_val.as<double>();
+  }
+  const int nr = std::max(1, p->dev.n_rot);
+  ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(n_slots) * nr);
+  db.phi = p->phi.as<double>();
+
+  hip_check(q2c::launch_init_product(db, p->occ.as<uint8_t>(), st), "init");
+  hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, d_shift_rot, d_shift_val, st), "angles");
+  const q2c::SvdParams sp = svd_params(ctx);
+  int launches = 0;
+  hip_check(hipEventRecord(ev.e[0], st), "event");
+  for (int g0 = 0; g0 < p->dev.n_gates; g0 += kGateChunk) {
+    const int g1 = std::min(p->dev.n_gates, g0 + kGateChunk);
+    hip_check(q2c::launch_gates(db, p->dev.gate_site, p->dev.gate_rot, p->dev.gate_pre, p->dev.gate_post, g0, g1,
+                                p->dev.n_rot, sp, st),
+              "gates");
+    ++launches;
+  }
+  hip_check(hipEventRecord(ev.e[1], st), "event");
+  hip_check(q2c::launch_envs(db, st), "envs");
+  hip_check(hipEventRecord(ev.e[2], st), "event");
+  const int ns = p->dev.n_strings;
+  ensure(ctx, p->ev_re, p->evr_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
+  ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
+  int n_wg = std::max(1, std::min(ns, 1024 / std::max(1, n_slots)));
+  if (n_wg < 4) n_wg = std::min(ns, 4);
+  const size_t scr = size_t(n_slots) * n_wg * 3 * size_t(B.cm) * B.cm * sizeof(double2);
+  ensure(ctx, p->scratch, p->scratch_cap, scr);
+  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->scratch.as<double2>(), n_wg, B.cm,
+                              p->ev_re.as<double>(), p->ev_im.as<double>(), st),
+            "pauli");
+  hip_check(hipEventRecord(ev.e[3], st), "event");
+  ensure(ctx, p->energies, p->en_cap, sizeof(double) * n_slots);
+  hip_check(q2c::launch_energy_reduce(db, p->dev.str_c, p->ev_re.as<double>(), p->ev_im.as<double>(), ns,
+                                      H.c_identity, p->energies.as<double>(), st),
+            "reduce");
+  hip_check(hipEventRecord(ev.e[4], st), "event");
+  std::vector<int> flags(n_slots);
+  stats_out.assign(size_t(n_slots) * q2c::kNStats, 0.0);
+  hip_check(hipMemcpyAsync(energies, p->energies.p, sizeof(double) * n_slots, hipMemcpyDeviceToHost, st), "copy E");
+  hip_check(hipMemcpyAsync(flags.data(), db.flags, sizeof(int) * n_slots, hipMemcpyDeviceToHost, st), "copy flags");
+  hip_check(hipMemcpyAsync(stats_out.data(), db.stats, sizeof(double) * n_slots * q2c::kNStats, hipMemcpyDeviceToHost, st),
+            "copy stats");
+  hip_check(hipStreamSynchronize(st), "sync");
+  pt.gate_ms += ev.ms(0, 1);
+  pt.env_ms += ev.ms(1, 2);
+  pt.pauli_ms += ev.ms(2, 3);
+  pt.reduce_ms += ev.ms(3, 4);
+  pt.gate_launches += launches;
+  pt.circuits += n_slots;
+  check_flags(flags);
+  for (int i = 0; i < n_slots; ++i)
+    if (!std::isfinite(energies[i])) throw StatusError(Q2C_ERR_NUMERIC, "non-finite energy");
+}
+
+void check_theta(const vqe_problem* p, const double* theta, int n_theta, int count) {
+  require(theta != nullptr || p->host.n_params == 0, "theta is NULL");
+  if (n_theta != p->host.n_params)
+    throw ArgError("n_theta (" + std::to_string(n_theta) + ") != number of UCCSD parameters (" +
+                   std::to_string(p->host.n_params) + ")");
+  for (long i = 0; i < long(count) * n_theta; ++i)
+    if (!std::isfinite(theta[i])) throw ArgError("non-finite theta");
+}
+
+void check_eval(const vqe_problem* p, int max_bond, int precision) {
+  require(p != nullptr, "NULL problem");
+  if (!p->ctx) throw ArgError("problem was compiled without a context (host-only)");
+  require(max_bond >= 1 && max_bond <= 256, "max_bond must be in 1..256");
+  require(precision == Q2C_FP64 || precision == Q2C_MIXED, "unknown precision");
+  if (precision == Q2C_MIXED) throw ArgError("Q2C_MIXED is not implemented in this build");
+}
+
+int chunk_slots(const vqe_problem* p) { return std::max(1, p->ctx->opts.slots); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ exports --
+
+extern "C" {
+
+const char* q2c_last_error(void) { return g_last_error.c_str(); }
+const char* q2c_version(void) { return "q2c 0.1 (gfx950, FP64)"; }
+
+int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx** out) {
+  return guarded([&] {
+    require(out != nullptr, "out is NULL");
+    int ndev = 0;
+    const hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0)
+      throw DeviceError(std::string("no HIP device available (") + hipGetErrorString(e) +
+                        "); a second HIP runtime loaded in this process also causes this");
+    require(device >= 0 && device < ndev, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      throw DeviceError(std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    auto c = std::make_unique<q2c_ctx>();
+    c->device = device;
+    c->activate();
+    q2c_opts o{};
+    if (opts) o = *opts;
+    if (o.max_sweeps <= 0) o.max_sweeps = 60;
+    if (!(o.sv_cutoff_rel > 0)) o.sv_cutoff_rel = 1e-12;
+    if (!(o.svd_tol > 0)) o.svd_tol = 1e-15;
+    if (o.slots <= 0) o.slots = 256;
+    if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = size_t(64) << 30;
+    require(o.sv_cutoff_rel < 1.0 && o.svd_tol < 1e-3, "bad tolerances");
+    c->opts = o;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+      c->own_stream = true;
+    }
+    *out = c.release();
+  });
+}
+
+int q2c_ctx_destroy(q2c_ctx* ctx) {
+  return guarded([&] {
+    require(ctx != nullptr, "NULL context");
+    ctx->activate();
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+  });
+}
+
+int mps_create(q2c_ctx* ctx, int n_qubits, int max_bond, int precision, const uint8_t* occ, mps_state** out) {
+  return guarded([&] {
+    require(ctx && out && occ, "NULL argument");
+    require(n_qubits >= 2 && n_qubits <= q2c::kMaxQubits, "n_qubits must be in 2..64");
+    require(max_bond >= 1 && max_bond <= 256, "max_bond must be in 1..256");
+    require(precision == Q2C_FP64 || precision == Q2C_MIXED, "unknown precision");
+    if (precision == Q2C_MIXED) throw ArgError("Q2C_MIXED is not implemented in this build");
+    for (int i = 0; i < n_qubits; ++i) require(occ[i] <= 1, "occ entries must be 0 or 1");
+    ctx->activate();
+    auto s = std::make_unique<mps_state>();
+    s->ctx = ctx;
+    s->n = n_qubits;
+    s->D = max_bond;
+    s->precision = precision;
+    s->batch = std::make_unique<Batch>(ctx, n_qubits, max_bond, 1);
+    s->occ = DBuf(ctx, n_qubits);
+    s->gsite = DBuf(ctx, sizeof(int));
+    s->grot = DBuf(ctx, sizeof(int));
+    s->gmat = DBuf(ctx, 32 * sizeof(double));
+    hip_check(hipMemcpyAsync(s->occ.p, occ, n_qubits, hipMemcpyHostToDevice, ctx->stream), "copy occ");
+    const int m1 = -1;
+    hip_check(hipMemcpyAsync(s->grot.p, &m1, sizeof(int), hipMemcpyHostToDevice, ctx->stream), "copy");
+    hip_check(q2c::launch_init_product(s->batch->d, s->occ.as<uint8_t>(), ctx->stream), "init");
+    hip_check(hipStreamSynchronize(ctx->stream), "sync");
+    *out = s.release();
+  });
+}
+
+int mps_destroy(mps_state* s) {
+  return guarded([&] {
+    require(s != nullptr, "NULL state");
+    s->ctx->activate();
+    (void)hipStreamSynchronize(s->ctx->stream);
+    delete s;
+  });
+}
+
+int mps_apply_gate(mps_state* s, int site, const double* gate, double* discarded_weight) {
+  return guarded([&] {
+    require(s && gate, "NULL argument");
+    require(site >= 0 && site <= s->n - 2, "site must be in 0..n_qubits-2");
+    for (int i = 0; i < 32; ++i) require(std::isfinite(gate[i]), "non-finite gate entry");
+    q2c_ctx* ctx = s->ctx;
+    ctx->activate();
+    hipStream_t st = ctx->stream;
+    std::vector<double> before(q2c::kNStats), after(q2c::kNStats);
+    q2c::DevBatch& db = s->batch->d;
+    hip_check(hipMemcpyAsync(s->gsite.p, &site, sizeof(int), hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(s->gmat.p, gate, 32 * sizeof(double), hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(before.data(), db.stats, sizeof(double) * q2c::kNStats, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(q2c::launch_gates(db, s->gsite.as<int>(), s->grot.as<int>(), s->gmat.as<double2>(),
+                                s->gmat.as<double2>(), 0, 1, 0, svd_params(ctx), st),
+              "gate");
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, db.flags, sizeof(int), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipMemcpyAsync(after.data(), db.stats, sizeof(double) * q2c::kNStats, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    check_flags({flag});
+    if (discarded_weight) *discarded_weight = after[q2c::kStatDisc] - before[q2c::kStatDisc];
+  });
+}
+
+int mps_expect_pauli_batch(mps_state* s, int n_strings, int n_words, const uint64_t* x_masks,
+                           const uint64_t* z_masks, double* out_re, double* out_im) {
+  return guarded([&] {
+    require(s && out_re, "NULL argument");
+    require(n_strings >= 0, "n_strings < 0");
+    require(n_words == (s->n + 63) / 64, "n_words must be ceil(n_qubits/64)");
+    if (n_strings == 0) return;
+    require(x_masks && z_masks, "NULL masks");
+    const uint64_t valid = s->n == 64 ? ~0ull : ((1ull << s->n) - 1);
+    for (int i = 0; i < n_strings; ++i)
+      require(((x_masks[i] | z_masks[i]) & ~valid) == 0, "mask bits beyond n_qubits");
+    q2c_ctx* ctx = s->ctx;
+    ctx->activate();
+    hipStream_t st = ctx->stream;
+    Batch& B = *s->batch;
+    s->sx = DBuf(ctx, sizeof(uint64_t) * n_strings);
+    s->sz = DBuf(ctx, sizeof(uint64_t) * n_strings);
+    s->ev_re = DBuf(ctx, sizeof(double) * n_strings);
+    s->ev_im = DBuf(ctx, sizeof(double) * n_strings);
+    hip_check(hipMemcpyAsync(s->sx.p, x_masks, sizeof(uint64_t) * n_strings, hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(s->sz.p, z_masks, sizeof(uint64_t) * n_strings, hipMemcpyHostToDevice, st), "copy");
+    const int n_wg = std::min(n_strings, 256);
+    if (s->scratch_wg < n_wg) {
+      s->scratch = DBuf(ctx, size_t(n_wg) * 3 * B.cm * B.cm * sizeof(double2));
+      s->scratch_wg = n_wg;
+    }
+    hip_check(q2c::launch_envs(B.d, st), "envs");
+    hip_check(q2c::launch_pauli(B.d, s->sx.as<uint64_t>(), s->sz.as<uint64_t>(), n_strings, s->scratch.as<double2>(),
+                                n_wg, B.cm, s->ev_re.as<double>(), s->ev_im.as<double>(), st),
+              "pauli");
+    hip_check(hipMemcpyAsync(out_re, s->ev_re.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
+    if (out_im) hip_check(hipMemcpyAsync(out_im, s->ev_im.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+  });
+}
+
+int mps_export(mps_state* s, int* chi_out, double* tensors, double* lambdas) {
+  return guarded([&] {
+    require(s && chi_out, "NULL argument");
+    q2c_ctx* ctx = s->ctx;
+    ctx->activate();
+    hipStream_t st = ctx->stream;
+    const q2c::DevBatch& b = s->batch->d;
+    const int N = s->n;
+    std::vector<double2> sites(b.site_stride);
+    std::vector<double> lam(b.lam_stride);
+    hip_check(hipMemcpyAsync(chi_out, b.chi, sizeof(int) * (N + 1), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipMemcpyAsync(sites.data(), b.sites, sizeof(double2) * b.site_stride, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipMemcpyAsync(lam.data(), b.lam, sizeof(double) * b.lam_stride, hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (tensors) {
+      size_t o = 0;
+      for (int n = 0; n < N; ++n) {
+        const int cl = chi_out[n], cr = chi_out[n + 1], capr = b.cap[n + 1];
+        for (int a = 0; a < cl; ++a)
+          for (int i = 0; i < 2; ++i)
+            for (int c = 0; c < cr; ++c) {
+              const double2 v = sites[b.site_off[n] + (long(2 * a + i)) * capr + c];
+              tensors[o++] = v.x;
+              tensors[o++] = v.y;
+            }
+      }
+    }
+    if (lambdas) {
+      size_t o = 0;
+      for (int bb = 0; bb < N - 1; ++bb)
+        for (int k = 0; k < chi_out[bb + 1]; ++k) lambdas[o++] = lam[b.lam_off[bb] + k];
+    }
+  });
+}
+
+int mps_get_stats(mps_state* s, q2c_stats* stats) {
+  return guarded([&] {
+    require(s && stats, "NULL argument");
+    s->ctx->activate();
+    std::vector<double> st(q2c::kNStats);
+    hip_check(hipMemcpy(st.data(), s->batch->d.stats, sizeof(double) * q2c::kNStats, hipMemcpyDeviceToHost), "copy");
+    fill_stats(stats, st, 1, 0.0);
+  });
+}
+
+int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1, const double* eri, double e_const,
+                       vqe_problem** out) {
+  return guarded([&] {
+    require(out != nullptr, "out is NULL");
+    auto p = std::make_unique<vqe_problem>();
+    p->host = q2c::compile_problem(n_orb, n_elec, h1, eri, e_const);
+    p->ctx = ctx;
+    if (ctx) {
+      ctx->activate();
+      hipStream_t st = ctx->stream;
+      const auto& H = p->host;
+      auto& d = p->dev;
+      d.n_qubits = H.n_qubits;
+      d.n_gates = int(H.gates.size());
+      d.n_rot = int(H.rotations.size());
+      d.n_strings = int(H.terms.size());
+      std::vector<int> site(d.n_gates), rot(d.n_gates);
+      std::vector<double2> pre(size_t(d.n_gates) * 16), post(size_t(d.n_gates) * 16);
+      for (int g = 0; g < d.n_gates; ++g) {
+        site[g] = H.gates[g].site;
+        rot[g] = H.gates[g].rot;
+        for (int i = 0; i < 16; ++i) {
+          pre[size_t(g) * 16 + i] = make_double2(H.gates[g].pre[i].real(), H.gates[g].pre[i].imag());
+          post[size_t(g) * 16 + i] = make_double2(H.gates[g].post[i].real(), H.gates[g].post[i].imag());
+        }
+      }
+      std::vector<double> rc(d.n_rot), sc(d.n_strings);
+      std::vector<int> rparam(d.n_rot);
+      std::vector<uint64_t> sx(d.n_strings), sz(d.n_strings);
+      for (int m = 0; m < d.n_rot; ++m) {
+        rc[m] = H.rotations[m].c;
+        rparam[m] = H.rotations[m].param;
+      }
+      for (int s = 0; s < d.n_strings; ++s) {
+        sx[s] = H.terms[s].x;
+        sz[s] = H.terms[s].z;
+        sc[s] = H.terms[s].c;
+      }
+      std::vector<uint8_t> occ(H.n_qubits);
+      for (int q = 0; q < H.n_qubits; ++q) occ[q] = q < H.n_elec ? 1 : 0;
+      auto up = [&](DBuf& buf, const void* src, size_t bytes) {
+        buf = DBuf(ctx, std::max<size_t>(bytes, 16));
+        if (bytes) hip_check(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, st), "upload");
+      };
+      up(p->gsite, site.data(), sizeof(int) * site.size());
+      up(p->grot, rot.data(), sizeof(int) * rot.size());
+      up(p->gpre, pre.data(), sizeof(double2) * pre.size());
+      up(p->gpost, post.data(), sizeof(double2) * post.size());
+      up(p->rc, rc.data(), sizeof(double) * rc.size());
+      up(p->rparam, rparam.data(), sizeof(int) * rparam.size());
+      up(p->sx, sx.data(), sizeof(uint64_t) * sx.size());
+      up(p->sz, sz.data(), sizeof(uint64_t) * sz.size());
+      up(p->sc, sc.data(), sizeof(double) * sc.size());
+      up(p->occ, occ.data(), occ.size());
+      d.gate_site = p->gsite.as<int>();
+      d.gate_rot = p->grot.as<int>();
+      d.gate_pre = p->gpre.as<double2>();
+      d.gate_post = p->gpost.as<double2>();
+      d.rot_c = p->rc.as<double>();
+      d.rot_param = p->rparam.as<int>();
+      d.str_x = p->sx.as<uint64_t>();
+      d.str_z = p->sz.as<uint64_t>();
+      d.str_c = p->sc.as<double>();
+      hip_check(hipStreamSynchronize(st), "sync");
+    }
+    *out = p.release();
+  });
+}
+
+int vqe_problem_destroy(vqe_problem* p) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    if (p->ctx) {
+      p->ctx->activate();
+      (void)hipStreamSynchronize(p->ctx->stream);
+    }
+    delete p;
+  });
+}
+
+int vqe_problem_info(const vqe_problem* p, int* n_qubits, int* n_params, int* n_strings, int* n_rotations,
+                     int* n_gates, double* identity_coeff) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    if (n_qubits) *n_qubits = p->host.n_qubits;
+    if (n_params) *n_params = p->host.n_params;
+    if (n_strings) *n_strings = int(p->host.terms.size());
+    if (n_rotations) *n_rotations = int(p->host.rotations.size());
+    if (n_gates) *n_gates = int(p->host.gates.size());
+    if (identity_coeff) *identity_coeff = p->host.c_identity;
+  });
+}
+
+int vqe_problem_paulis(const vqe_problem* p, uint64_t* x, uint64_t* z, double* coeff) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    const auto& t = p->host.terms;
+    for (size_t i = 0; i < t.size(); ++i) {
+      if (x) x[i] = t[i].x;
+      if (z) z[i] = t[i].z;
+      if (coeff) coeff[i] = t[i].c;
+    }
+  });
+}
+
+int vqe_problem_rotations(const vqe_problem* p, uint64_t* x, uint64_t* z, double* c, int* param) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    const auto& r = p->host.rotations;
+    for (size_t i = 0; i < r.size(); ++i) {
+      if (x) x[i] = r[i].x;
+      if (z) z[i] = r[i].z;
+      if (c) c[i] = r[i].c;
+      if (param) param[i] = r[i].param;
+    }
+  });
+}
+
+int vqe_problem_gates(const vqe_problem* p, int* site, int* rot, double* pre, double* post) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    const auto& g = p->host.gates;
+    for (size_t i = 0; i < g.size(); ++i) {
+      if (site) site[i] = g[i].site;
+      if (rot) rot[i] = g[i].rot;
+      for (int k = 0; k < 16; ++k) {
+        if (pre) {
+          pre[i * 32 + 2 * k] = g[i].pre[k].real();
+          pre[i * 32 + 2 * k + 1] = g[i].pre[k].imag();
+        }
+        if (post) {
+          post[i * 32 + 2 * k] = g[i].post[k].real();
+          post[i * 32 + 2 * k + 1] = g[i].post[k].imag();
+        }
+      }
+    }
+  });
+}
+
+int vqe_energy(vqe_problem* p, const double* theta, int n_theta, int max_bond, int precision, double* energy,
+               q2c_stats* stats) {
+  return guarded([&] {
+    check_eval(p, max_bond, precision);
+    require(energy != nullptr, "energy is NULL");
+    check_theta(p, theta, n_theta, 1);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> st;
+    PhaseTimes pt;
+    double e = 0.0;
+    run_circuits(p, max_bond, theta, 1, nullptr, nullptr, &e, st, pt);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *energy = e;
+    fill_stats(stats, st, 1, secs, pt);
+  });
+}
+
+int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_theta, int max_bond, int precision,
+                     double* energies, q2c_stats* stats) {
+  return guarded([&] {
+    check_eval(p, max_bond, precision);
+    require(energies != nullptr, "energies is NULL");
+    require(n_batch >= 1, "n_batch must be >= 1");
+    check_theta(p, theta, n_theta, n_batch);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> out(n_batch), all_st, st;
+    PhaseTimes pt;
+    const int chunk = chunk_slots(p);
+    for (int b0 = 0; b0 < n_batch; b0 += chunk) {
+      const int nb = std::min(chunk, n_batch - b0);
+      run_circuits(p, max_bond, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st, pt);
+      all_st.insert(all_st.end(), st.begin(), st.end());
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::copy(out.begin(), out.end(), energies);
+    fill_stats(stats, all_st, n_batch, secs, pt);
+  });
+}
+
+namespace {
+void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+                    std::vector<double>& ep, std::vector<double>& em, double* base, std::vector<double>& all_st,
+                    PhaseTimes& pt) {
+  // circuits: (rot, +pi/2), (rot, -pi/2) for each listed rotation, then the base circuit if requested
+  const int np = p->host.n_params;
+  std::vector<int> srot;
+  std::vector<double> sval;
+  for (int m : rots) {
+    srot.push_back(m);
+    sval.push_back(0.5 * M_PI);
+    srot.push_back(m);
+    sval.push_back(-0.5 * M_PI);
+  }
+  if (base) {
+    srot.push_back(-1);
+    sval.push_back(0.0);
+  }
+  const int total = int(srot.size());
+  std::vector<double> en(total), st;
+  const int chunk = chunk_slots(p);
+  std::vector<double> th(size_t(chunk) * np);
+  for (int b0 = 0; b0 < total; b0 += chunk) {
+    const int nb = std::min(chunk, total - b0);
+    for (int i = 0; i < nb; ++i) std::copy(theta, theta + np, th.begin() + size_t(i) * np);
+    run_circuits(p, max_bond, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st, pt);
+    all_st.insert(all_st.end(), st.begin(), st.end());
+  }
+  ep.resize(rots.size());
+  em.resize(rots.size());
+  for (size_t i = 0; i < rots.size(); ++i) {
+    ep[i] = en[2 * i];
+    em[i] = en[2 * i + 1];
+  }
+  if (base) *base = en[total - 1];
+}
+}  // namespace
+
+int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int max_bond, int precision, double* grad,
+                        double* energy, q2c_stats* stats) {
+  return guarded([&] {
+    check_eval(p, max_bond, precision);
+    require(grad != nullptr, "grad is NULL");
+    check_theta(p, theta, n_theta, 1);
+    const auto t0 = std::chrono::steady_clock::now();
+    const auto& R = p->host.rotations;
+    std::vector<int> rots(R.size());
+    for (size_t m = 0; m < R.size(); ++m) rots[m] = int(m);
+    std::vector<double> ep, em, all_st;
+    PhaseTimes pt;
+    double base = 0.0;
+    shift_energies(p, theta, rots, max_bond, ep, em, energy ? &base : nullptr, all_st, pt);
+    std::vector<double> g(n_theta, 0.0);
+    for (size_t m = 0; m < R.size(); ++m) g[R[m].param] += -2.0 * R[m].c * 0.5 * (ep[m] - em[m]);
+    std::copy(g.begin(), g.end(), grad);
+    if (energy) *energy = base;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, all_st, int(all_st.size() / q2c::kNStats), secs, pt);
+  });
+}
+
+int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const int* rot_idx, int n_rot, int max_bond,
+                       int precision, double* e_plus, double* e_minus, q2c_stats* stats) {
+  return guarded([&] {
+    check_eval(p, max_bond, precision);
+    require(rot_idx && e_plus && e_minus, "NULL argument");
+    require(n_rot >= 1, "n_rot must be >= 1");
+    check_theta(p, theta, n_theta, 1);
+    std::vector<int> rots(rot_idx, rot_idx + n_rot);
+    for (int m : rots) require(m >= 0 && m < int(p->host.rotations.size()), "rotation index out of range");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<double> ep, em, all_st;
+    PhaseTimes pt;
+    shift_energies(p, theta, rots, max_bond, ep, em, nullptr, all_st, pt);
+    std::copy(ep.begin(), ep.end(), e_plus);
+    std::copy(em.begin(), em.end(), e_minus);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_stats(stats, all_st, int(all_st.size() / q2c::kNStats), secs, pt);
+  });
+}
+
+}  // extern "C"

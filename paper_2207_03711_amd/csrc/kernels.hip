@@ -1,0 +1,689 @@
+// HIP kernels for gfx950: MPS gate application (contraction, FP64 SVD,
+// truncation, update), identity environments, Pauli transfer sweeps and the
+// compensated energy sum.  One workgroup owns one MPS slot, so a batch of
+// independent circuits runs as a grid of workgroups.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "engine.hpp"
+
+namespace q2c {
+
+// ------------------------------------------------------------ helpers ----
+
+__device__ __forceinline__ double2 cmk(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return cmk(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return cmk(a.x * s, a.y * s); }
+// acc += a * b
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block (deterministic order); red needs kBlock/64 doubles.
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+// Block-level complex GEMM: C = alpha * op(A) * op(B) (+ C if accumulate).
+// op(A)[i][k] = TA ? conj(A[k*lda+i]) : A[i*lda+k]
+// op(B)[k][j] = TB ? conj(B[j*ldb+k]) : B[k*ldb+j]
+// lds: 2*64*8 double2.  All threads of the block must call it.
+template <bool TA, bool TB>
+__device__ void bgemm(int M, int N, int K, const double2* __restrict__ A, int lda,
+                      const double2* __restrict__ B, int ldb, double2* __restrict__ C, int ldc,
+                      double2 alpha, bool accumulate, double2* lds) {
+  constexpr int BM = 64, BN = 64, BK = 8;
+  double2* As = lds;
+  double2* Bs = lds + BK * BM;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;  // 16 x 32 threads
+  __syncthreads();
+  for (int i0 = 0; i0 < M; i0 += BM) {
+    for (int j0 = 0; j0 < N; j0 += BN) {
+      double2 acc[2][4];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = cmk(0.0, 0.0);
+      for (int k0 = 0; k0 < K; k0 += BK) {
+        {
+          const int r = tid >> 3, k = tid & 7;
+          const int gi = i0 + r, gk = k0 + k;
+          double2 v = cmk(0.0, 0.0);
+          if (gi < M && gk < K) v = TA ? cconj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
+          As[k * BM + r] = v;
+        }
+        {
+          const int k = tid >> 6, c = tid & 63;
+          const int gk = k0 + k, gj = j0 + c;
+          double2 v = cmk(0.0, 0.0);
+          if (gk < K && gj < N) v = TB ? cconj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
+          Bs[k * BN + c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+          const double2 a0 = As[k * BM + ty * 2], a1 = As[k * BM + ty * 2 + 1];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double2 bv = Bs[k * BN + tx * 4 + q];
+            cfma(acc[0][q], a0, bv);
+            cfma(acc[1][q], a1, bv);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gi = i0 + ty * 2 + r, gj = j0 + tx * 4 + q;
+          if (gi < M && gj < N) {
+            double2 v = cmul(alpha, acc[r][q]);
+            double2* dst = &C[(long)gi * ldc + gj];
+            *dst = accumulate ? cadd(*dst, v) : v;
+          }
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Householder vector for a row (conj=true: reflector applied from the
+// right to rows, built from conj(x)) or a column (conj=false).
+// Given x (len L) returns u with H = I - u u^H mapping x -> -ph*|x| e_0 and
+// writes beta = -ph*|x| (the new leading entry; for rows the entry stored in
+// the row is beta as well).  Executed by one wave; u written to dst.
+__device__ void wave_householder(const double2* x, int L, bool rowform, double2* dst, double2* beta_out,
+                                 bool* zero_out) {
+  const int lane = threadIdx.x & 63;
+  double nrm2 = 0.0;
+  for (int j = lane; j < L; j += 64) nrm2 += cabs2(x[j]);
+  nrm2 = wave_sum(nrm2);
+  const double nx = sqrt(nrm2);
+  const double2 x0 = x[0];
+  const double ax = sqrt(cabs2(x0));
+  const double2 ph = ax > 0.0 ? cscale(x0, 1.0 / ax) : cmk(1.0, 0.0);
+  if (nx == 0.0) {
+    for (int j = lane; j < L; j += 64) dst[j] = cmk(0.0, 0.0);
+    if (lane == 0) {
+      *beta_out = cmk(0.0, 0.0);
+      *zero_out = true;
+    }
+    return;
+  }
+  const double inv = 1.0 / sqrt(nx * (nx + ax));
+  for (int j = lane; j < L; j += 64) {
+    double2 v = x[j];
+    if (j == 0) v = cscale(ph, ax + nx);
+    if (rowform) v = cconj(v);
+    dst[j] = cscale(v, inv);
+  }
+  if (lane == 0) {
+    *beta_out = cscale(ph, -nx);
+    *zero_out = false;
+  }
+}
+
+// ---------------------------------------------------------- init / angles --
+
+__global__ void k_init_product(DevBatch b, const uint8_t* occ) {
+  const int slot = blockIdx.x;
+  const int N = b.n_qubits;
+  double2* sites = b.sites + slot * b.site_stride;
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    double2* B = sites + b.site_off[n];
+    const int o = occ[n] ? 1 : 0;
+    // chi_l = chi_r = 1: element [0][i][0] at i * cap_r
+    B[0] = cmk(o == 0 ? 1.0 : 0.0, 0.0);
+    B[b.cap[n + 1]] = cmk(o == 1 ? 1.0 : 0.0, 0.0);
+  }
+  for (int i = threadIdx.x; i <= N; i += blockDim.x) b.chi[slot * (N + 1) + i] = 1;
+  for (int n = threadIdx.x; n < N - 1; n += blockDim.x) b.lam[slot * b.lam_stride + b.lam_off[n]] = 1.0;
+  if (threadIdx.x < kNStats) b.stats[slot * kNStats + threadIdx.x] = 0.0;
+  if (threadIdx.x == 0) {
+    b.stats[slot * kNStats + kStatMaxChi] = 1.0;
+    b.flags[slot] = 0;
+  }
+}
+
+__global__ void k_angles(double* phi, int n_rot, const double* rot_c, const int* rot_param,
+                         const double* theta, int n_theta, const int* shift_rot, const double* shift_val) {
+  const int slot = blockIdx.y;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_rot) return;
+  double v = -2.0 * rot_c[m] * theta[(long)slot * n_theta + rot_param[m]];
+  if (shift_rot && shift_rot[slot] == m) v += shift_val[slot];
+  phi[(long)slot * n_rot + m] = v;
+}
+
+// ----------------------------------------------------------- gate kernel --
+
+struct SlotView {
+  double2* sites;
+  double* lam;
+  int* chi;
+  double2 *M, *A, *H, *W;
+  double* S;
+  int* P;
+  double* stats;
+  int* flags;
+};
+
+__device__ SlotView slot_view(const DevBatch& b, int slot) {
+  SlotView v;
+  v.sites = b.sites + slot * b.site_stride;
+  v.lam = b.lam + slot * b.lam_stride;
+  v.chi = b.chi + slot * (b.n_qubits + 1);
+  v.M = b.wsM + slot * b.ws_stride;
+  v.A = b.wsA + slot * b.ws_stride;
+  v.H = b.wsH + slot * b.ws_stride;
+  v.W = b.wsW + slot * b.ws_stride;
+  v.S = b.wsS + slot * 2 * b.ws;
+  v.P = b.wsP + slot * b.ws;
+  v.stats = b.stats + slot * kNStats;
+  v.flags = b.flags + slot;
+  return v;
+}
+
+// Circle-method round-robin: position -> row in round t (P even).
+__device__ __forceinline__ int rr_row(int pos, int t, int P) {
+  return pos == 0 ? 0 : 1 + ((pos - 1 + t) % (P - 1));
+}
+
+constexpr int kMaxPerLane = 8;  // row length <= 512
+
+__global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restrict__ gsite,
+                                                  const int* __restrict__ grot, const double2* __restrict__ gpre,
+                                                  const double2* __restrict__ gpost, const double* __restrict__ phi_all,
+                                                  int n_rot, int g0, int g1, SvdParams sp) {
+  __shared__ double2 lds_gemm[2 * 64 * 8];
+  __shared__ double2 O[16];
+  __shared__ double2 uq[512];  // column reflector (length <= 2 * max bond)
+  __shared__ double red[kBlock / 64];
+  __shared__ double2 sbeta;
+  __shared__ bool szero;
+  __shared__ int srot;
+  __shared__ int sabort;
+
+  const int slot = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  SlotView v = slot_view(b, slot);
+  const double* phi = phi_all ? phi_all + (long)slot * n_rot : nullptr;
+  if (tid == 0) sabort = (*v.flags & kFlagNumeric) ? 1 : 0;
+  __syncthreads();
+  if (sabort) return;
+
+  for (int g = g0; g < g1; ++g) {
+    const int n = gsite[g];
+    const int rot = grot[g];
+    if (tid < 16) {
+      if (rot < 0) {
+        O[tid] = gpre[(long)g * 16 + tid];
+      } else {
+        const double ph = phi[rot];
+        const double2 dm = cmk(cos(0.5 * ph), -sin(0.5 * ph));  // exp(-i phi/2)
+        const double2 dp = cmk(cos(0.5 * ph), sin(0.5 * ph));   // exp(+i phi/2)
+        const int i = tid >> 2, j = tid & 3;
+        double2 s = cmk(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) {
+          const double2 d = (k & 1) ? dp : dm;
+          cfma(s, cmul(gpost[(long)g * 16 + i * 4 + k], d), gpre[(long)g * 16 + k * 4 + j]);
+        }
+        O[tid] = s;
+      }
+    }
+    const int chil = v.chi[n], chim = v.chi[n + 1], chir = v.chi[n + 2];
+    const int capl_r = b.cap[n + 1];   // capacity of bond n (right bond of site n)
+    const int capr_r = b.cap[n + 2];   // capacity of bond n+1
+    double2* Bn = v.sites + b.site_off[n];
+    double2* Bn1 = v.sites + b.site_off[n + 1];
+    const int m = 2 * chil, nn = 2 * chir;
+    __syncthreads();
+
+    // ---- Phase A: Theta = Bn * Bn1 (Eq. 7 before the gate), per j ---------
+    for (int j = 0; j < 2; ++j)
+      bgemm<false, false>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, v.M + j * chir, nn,
+                          cmk(1.0, 0.0), false, lds_gemm);
+    // gate mixing (Eq. 7) and lambda scaling (Eq. 8)
+    for (int idx = tid; idx < chil * chir; idx += blockDim.x) {
+      const int a = idx / chir, c = idx - a * chir;
+      double2 t[4];
+#pragma unroll
+      for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+        for (int jp = 0; jp < 2; ++jp) t[2 * ip + jp] = v.M[(long)(2 * a + ip) * nn + jp * chir + c];
+      const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + a];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          double2 s = cmk(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cfma(s, O[(2 * i + jj) * 4 + q], t[q]);
+          const long off = (long)(2 * a + i) * nn + jj * chir + c;
+          v.M[off] = s;
+          v.A[off] = cscale(s, la);
+        }
+    }
+    __syncthreads();
+
+    // ---- Phase B: SVD of A = M' (m x nn), Eq. 9 -----------------------------
+    const int r = m < nn ? m : nn;
+    // B1: LQ, A <- A H_0 H_1 ... (reflectors on rows, stored in H)
+    for (int k = 0; k < r; ++k) {
+      if (wave == 0) {
+        wave_householder(v.A + (long)k * nn + k, nn - k, true, v.H + (long)k * nn + k, &sbeta, &szero);
+      }
+      __syncthreads();
+      if (!szero) {
+        for (int a = k + 1 + wave; a < m; a += nwaves) {
+          double2* row = v.A + (long)a * nn;
+          const double2* u = v.H + (long)k * nn;
+          double wr = 0.0, wi = 0.0;
+          for (int j = k + lane; j < nn; j += 64) {
+            const double2 p = cmul(row[j], u[j]);
+            wr += p.x;
+            wi += p.y;
+          }
+          const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+          for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
+        }
+      }
+      // row k itself
+      for (int j = k + tid; j < nn; j += blockDim.x) v.A[(long)k * nn + j] = j == k ? sbeta : cmk(0.0, 0.0);
+      __syncthreads();
+    }
+    // B2: QR of the m x r lower-trapezoidal L (reflectors on columns)
+    for (int k = 0; k < r; ++k) {
+      const int L = m - k;
+      for (int i = tid; i < L; i += blockDim.x) uq[i] = v.A[(long)(k + i) * nn + k];
+      __syncthreads();
+      if (wave == 0) wave_householder(uq, L, false, uq, &sbeta, &szero);
+      __syncthreads();
+      if (!szero) {
+        for (int c = k + 1 + wave; c < r; c += nwaves) {
+          double wr = 0.0, wi = 0.0;
+          for (int i = lane; i < L; i += 64) {
+            const double2 p = cmul(cconj(uq[i]), v.A[(long)(k + i) * nn + c]);
+            wr += p.x;
+            wi += p.y;
+          }
+          const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+          for (int i = lane; i < L; i += 64) {
+            double2* e = &v.A[(long)(k + i) * nn + c];
+            *e = csub(*e, cmul(uq[i], w));
+          }
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < L; i += blockDim.x) v.A[(long)(k + i) * nn + k] = i == 0 ? sbeta : cmk(0.0, 0.0);
+      __syncthreads();
+    }
+    // B3: one-sided Jacobi on the rows of the r x r upper triangle
+    int sweeps = 0;
+    bool converged = r < 2;
+    if (r >= 2) {
+      const int Pe = r + (r & 1);
+      for (int sw = 0; sw < sp.max_sweeps; ++sw) {
+        if (tid == 0) srot = 0;
+        __syncthreads();
+        for (int t = 0; t < Pe - 1; ++t) {
+          for (int kp = wave; kp < Pe / 2; kp += nwaves) {
+            const int p = rr_row(kp, t, Pe), q = rr_row(Pe - 1 - kp, t, Pe);
+            if (p >= r || q >= r) continue;
+            double2* rp = v.A + (long)p * nn;
+            double2* rq = v.A + (long)q * nn;
+            double2 xp[kMaxPerLane], xq[kMaxPerLane];
+            double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+            for (int e = 0; e < kMaxPerLane; ++e) {
+              const int j = lane + 64 * e;
+              if (j < r) {
+                xp[e] = rp[j];
+                xq[e] = rq[j];
+              } else {
+                xp[e] = cmk(0.0, 0.0);
+                xq[e] = cmk(0.0, 0.0);
+              }
+              al += cabs2(xp[e]);
+              be += cabs2(xq[e]);
+              // gamma = sum p_j conj(q_j)
+              gr += xp[e].x * xq[e].x + xp[e].y * xq[e].y;
+              gi += xp[e].y * xq[e].x - xp[e].x * xq[e].y;
+            }
+            al = wave_sum(al);
+            be = wave_sum(be);
+            gr = wave_sum(gr);
+            gi = wave_sum(gi);
+            const double ag = sqrt(gr * gr + gi * gi);
+            if (!(al > 0.0 && be > 0.0) || !(ag > sp.tol * sqrt(al) * sqrt(be))) continue;
+            const double zeta = (be - al) / (2.0 * ag);
+            double tt;
+            if (fabs(zeta) > 1e150)
+              tt = 0.5 / zeta;
+            else
+              tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+            const double2 e_ip = cmk(gr / ag, gi / ag);  // gamma / |gamma|
+            const double2 s_ip = cscale(e_ip, sn);       // s e^{i phi}
+            const double2 s_im = cconj(s_ip);             // s e^{-i phi}
+#pragma unroll
+            for (int e = 0; e < kMaxPerLane; ++e) {
+              const int j = lane + 64 * e;
+              if (j < r) {
+                const double2 np = csub(cscale(xp[e], cs), cmul(s_ip, xq[e]));
+                const double2 nq = cadd(cmul(s_im, xp[e]), cscale(xq[e], cs));
+                rp[j] = np;
+                rq[j] = nq;
+              }
+            }
+            if (lane == 0) srot = 1;
+          }
+          __syncthreads();
+        }
+        sweeps = sw + 1;
+        const int any = srot;
+        __syncthreads();
+        if (!any) {
+          converged = true;
+          break;
+        }
+      }
+    }
+    // B4: back-transform rows: [F, 0] H_{r-1} ... H_0 -> s_k w_k^H
+    for (int a = wave; a < r; a += nwaves) {
+      double2* row = v.A + (long)a * nn;
+      for (int j = r + lane; j < nn; j += 64) row[j] = cmk(0.0, 0.0);
+      for (int k = r - 1; k >= 0; --k) {
+        const double2* u = v.H + (long)k * nn;
+        double wr = 0.0, wi = 0.0;
+        for (int j = k + lane; j < nn; j += 64) {
+          const double2 p = cmul(row[j], u[j]);
+          wr += p.x;
+          wi += p.y;
+        }
+        const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+        for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
+      }
+      double s2 = 0.0;
+      for (int j = lane; j < nn; j += 64) s2 += cabs2(row[j]);
+      s2 = wave_sum(s2);
+      if (lane == 0) v.S[a] = sqrt(s2);
+    }
+    __syncthreads();
+
+    // ---- Phase C: truncate (Eq. 9), update (Eq. 10) --------------------------
+    for (int a = tid; a < r; a += blockDim.x) {
+      const double sa = v.S[a];
+      int rank = 0;
+      for (int q = 0; q < r; ++q) {
+        const double sq = v.S[q];
+        rank += (sq > sa || (sq == sa && q < a)) ? 1 : 0;
+      }
+      v.P[rank] = a;
+    }
+    __syncthreads();
+    __shared__ int schi;
+    __shared__ double snorm;
+    if (tid == 0) {
+      const double s1 = v.S[v.P[0]];
+      if (!(s1 > 0.0) || !isfinite(s1)) {
+        *v.flags |= kFlagNumeric;
+        sabort = 1;
+      } else {
+        int nz = 0;
+        for (int q = 0; q < r; ++q) nz += v.S[q] > sp.cutoff_rel * s1 ? 1 : 0;
+        const int keep = nz < b.max_bond ? nz : b.max_bond;
+        double kept = 0.0, disc = 0.0;
+        for (int q = 0; q < r; ++q) {
+          const double s = v.S[v.P[q]];
+          if (q < keep)
+            kept += s * s;
+          else
+            disc += s * s;
+        }
+        const double d = disc / (kept + disc);
+        schi = keep;
+        snorm = sqrt(kept);
+        v.stats[kStatDisc] += d;
+        if (d > v.stats[kStatMaxDisc]) v.stats[kStatMaxDisc] = d;
+        if (keep > v.stats[kStatMaxChi]) v.stats[kStatMaxChi] = keep;
+        if (sweeps > v.stats[kStatSweeps]) v.stats[kStatSweeps] = sweeps;
+        v.stats[kStatSweepSum] += sweeps;
+        {
+          const double cl = chil, cmd = chim, cr = chir;
+          const double mm = m > nn ? m : nn, nm = m > nn ? nn : m;
+          v.stats[kStatFlops] += 32.0 * cl * cmd * cr + 128.0 * cl * cr + 4.0 * (4.0 * mm * nm * nm + 8.0 * nm * nm * nm) +
+                                 8.0 * double(m) * double(nn) * keep;
+        }
+        if (!converged) *v.flags |= kFlagNoConv;
+      }
+    }
+    __syncthreads();
+    if (sabort) return;
+    const int keep = schi;
+    const double nrm = snorm;
+    // sorted, normalised rows -> W (keep x nn) and site n+1 (Eq. 10: B_{n+1} = V)
+    for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
+      const int k = idx / nn, col = idx - k * nn;
+      const int src = v.P[k];
+      const double2 w = cscale(v.A[(long)src * nn + col], 1.0 / v.S[src]);
+      v.W[idx] = w;
+      const int jj = col / chir, c = col - jj * chir;
+      Bn1[(long)(2 * k + jj) * capr_r + c] = w;
+    }
+    for (int k = tid; k < keep; k += blockDim.x) v.lam[b.lam_off[n] + k] = v.S[v.P[k]] / nrm;
+    __syncthreads();
+    // B_n = M W^H / ||S_kept||  (Eq. 10, no division by Schmidt values)
+    bgemm<false, true>(m, keep, nn, v.M, nn, v.W, nn, Bn, capl_r, cmk(1.0 / nrm, 0.0), false, lds_gemm);
+    if (tid == 0) v.chi[n + 1] = keep;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- environments --
+
+// L[0] = 1; L[k+1] = sum_i B_i^H L[k] B_i.   Rt[N] = 1; Rt[k] = sum_i B_i Rt[k+1] B_i^H.
+__global__ __launch_bounds__(kBlock) void k_envs(DevBatch b) {
+  __shared__ double2 lds_gemm[2 * 64 * 8];
+  const int slot = blockIdx.x;
+  const int N = b.n_qubits;
+  SlotView v = slot_view(b, slot);
+  double2* L = b.envL + slot * b.env_stride;
+  double2* R = b.envR + slot * b.env_stride;
+  double2* X = v.M;  // scratch
+  if (threadIdx.x == 0) {
+    L[b.env_off[0]] = cmk(1.0, 0.0);
+    R[b.env_off[N]] = cmk(1.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    const int cl = v.chi[k], cr = v.chi[k + 1];
+    const int capl = b.cap[k], capr = b.cap[k + 1];
+    const double2* Bk = v.sites + b.site_off[k];
+    for (int i = 0; i < 2; ++i) {
+      bgemm<false, false>(cl, cr, cl, L + b.env_off[k], capl, Bk + i * capr, 2 * capr, X, cr, cmk(1.0, 0.0),
+                          false, lds_gemm);
+      bgemm<true, false>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cr, L + b.env_off[k + 1], capr,
+                         cmk(1.0, 0.0), i == 1, lds_gemm);
+    }
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    const int cl = v.chi[k], cr = v.chi[k + 1];
+    const int capl = b.cap[k], capr = b.cap[k + 1];
+    const double2* Bk = v.sites + b.site_off[k];
+    for (int i = 0; i < 2; ++i) {
+      bgemm<false, false>(cl, cr, cr, Bk + i * capr, 2 * capr, R + b.env_off[k + 1], capr, X, cr, cmk(1.0, 0.0),
+                          false, lds_gemm);
+      bgemm<false, true>(cl, cl, cr, X, cr, Bk + i * capr, 2 * capr, R + b.env_off[k], capl, cmk(1.0, 0.0),
+                         i == 1, lds_gemm);
+    }
+  }
+  if (threadIdx.x == 0) v.stats[kStatNorm] = L[b.env_off[N]].x;
+}
+
+// --------------------------------------------------------- Pauli sweeps ---
+
+__global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __restrict__ sx,
+                                                  const uint64_t* __restrict__ sz, int n_strings,
+                                                  double2* scratch, int cm, double* ev_re, double* ev_im) {
+  __shared__ double2 lds_gemm[2 * 64 * 8];
+  __shared__ double red[kBlock / 64];
+  const int slot = blockIdx.y;
+  const int N = b.n_qubits;
+  SlotView v = slot_view(b, slot);
+  const double2* L = b.envL + slot * b.env_stride;
+  const double2* R = b.envR + slot * b.env_stride;
+  double2* T0 = scratch + ((long)slot * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
+  double2* T1 = T0 + (long)cm * cm;
+  double2* X = T1 + (long)cm * cm;
+  const double nrm = L[b.env_off[N]].x;
+  for (int s = blockIdx.x; s < n_strings; s += gridDim.x) {
+    const uint64_t x = sx[s], z = sz[s];
+    const uint64_t mk = x | z;
+    double2 ev = cmk(0.0, 0.0);
+    if (mk == 0) {
+      ev = cmk(1.0, 0.0);
+    } else {
+      const int lo = __builtin_ctzll(mk), hi = 63 - __builtin_clzll(mk);
+      const int c0 = v.chi[lo];
+      const double2* Llo = L + b.env_off[lo];
+      for (int idx = threadIdx.x; idx < c0 * c0; idx += blockDim.x) {
+        const int a = idx / c0, c = idx - a * c0;
+        T0[(long)a * cm + c] = Llo[(long)a * b.cap[lo] + c];
+      }
+      __syncthreads();
+      double2* T = T0;
+      double2* Tn = T1;
+      for (int k = lo; k <= hi; ++k) {
+        const int cl = v.chi[k], cr = v.chi[k + 1];
+        const int capr = b.cap[k + 1];
+        const double2* Bk = v.sites + b.site_off[k];
+        const int xb = (x >> k) & 1, zb = (z >> k) & 1;
+        for (int i = 0; i < 2; ++i) {
+          const int ip = xb ? 1 - i : i;
+          double2 ph = cmk(1.0, 0.0);
+          if (zb && !xb) ph = i == 0 ? cmk(1.0, 0.0) : cmk(-1.0, 0.0);  // Z
+          if (zb && xb) ph = i == 0 ? cmk(0.0, -1.0) : cmk(0.0, 1.0);   // Y: <0|Y|1> = -i
+          bgemm<false, false>(cl, cr, cl, T, cm, Bk + ip * capr, 2 * capr, X, cm, cmk(1.0, 0.0), false, lds_gemm);
+          bgemm<true, false>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1, lds_gemm);
+        }
+        double2* t = T;
+        T = Tn;
+        Tn = t;
+      }
+      // <P> = sum_{c,c'} T[c][c'] R[c][c'],  R[c][c'] = Rt[c'][c]
+      const int ch = v.chi[hi + 1];
+      const double2* Rh = R + b.env_off[hi + 1];
+      const int ldr = b.cap[hi + 1];
+      double pr = 0.0, pi = 0.0;
+      for (int idx = threadIdx.x; idx < ch * ch; idx += blockDim.x) {
+        const int a = idx / ch, c = idx - a * ch;
+        const double2 p = cmul(T[(long)a * cm + c], Rh[(long)c * ldr + a]);
+        pr += p.x;
+        pi += p.y;
+      }
+      pr = block_sum(pr, red);
+      pi = block_sum(pi, red);
+      ev = cmk(pr / nrm, pi / nrm);
+    }
+    if (threadIdx.x == 0) {
+      ev_re[(long)slot * n_strings + s] = ev.x;
+      ev_im[(long)slot * n_strings + s] = ev.y;
+    }
+    __syncthreads();
+  }
+}
+
+// Neumaier-compensated sum in term order, identity coefficient last.
+__global__ void k_energy_reduce(const double* coeff, const double* ev_re, const double* ev_im, int n_strings,
+                                double c_identity, double* energy, double* stats) {
+  const int slot = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s = 0.0, comp = 0.0, mi = 0.0;
+  auto add = [&](double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x))
+      comp += (s - t) + x;
+    else
+      comp += (x - t) + s;
+    s = t;
+  };
+  for (int i = 0; i < n_strings; ++i) {
+    add(coeff[i] * ev_re[(long)slot * n_strings + i]);
+    mi = fmax(mi, fabs(ev_im[(long)slot * n_strings + i]));
+  }
+  add(c_identity);
+  energy[slot] = s + comp;
+  stats[slot * kNStats + kStatMaxImag] = mi;
+}
+
+// --------------------------------------------------------------- launchers --
+
+hipError_t launch_init_product(const DevBatch& b, const uint8_t* d_occ, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_product, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
+  return hipGetLastError();
+}
+
+hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d_theta, int n_theta,
+                         const int* d_shift_rot, const double* d_shift_val, hipStream_t st) {
+  if (p.n_rot == 0) return hipSuccess;
+  dim3 grid((p.n_rot + 255) / 256, b.n_slots);
+  hipLaunchKernelGGL(k_angles, grid, dim3(256), 0, st, b.phi, p.n_rot, p.rot_c, p.rot_param, d_theta, n_theta,
+                     d_shift_rot, d_shift_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, const double2* d_pre,
+                        const double2* d_post, int g0, int g1, int n_rot, SvdParams sp, hipStream_t st) {
+  if (g1 <= g0) return hipSuccess;
+  hipLaunchKernelGGL(k_gates, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot,
+                     g0, g1, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_envs(const DevBatch& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_envs, dim3(b.n_slots), dim3(kBlock), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings, double2* d_scratch,
+                        int n_wg, int cm, double* d_ev_re, double* d_ev_im, hipStream_t st) {
+  if (n_strings == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pauli, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch, cm,
+                     d_ev_re, d_ev_im);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(const DevBatch& b, const double* d_coeff, const double* d_ev_re, const double* d_ev_im,
+                                int n_strings, double c_identity, double* d_energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(b.n_slots), dim3(64), 0, st, d_coeff, d_ev_re, d_ev_im, n_strings,
+                     c_identity, d_energy, b.stats);
+  return hipGetLastError();
+}
+
+}  // namespace q2c

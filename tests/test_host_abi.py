@@ -1,0 +1,137 @@
+"""Host-side checks of libq2c that need no GPU: exported symbols, the C++
+problem compiler against the independently written oracle, and the error
+conventions of the C ABI."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fermion, uccsd
+from workloads import CONFIGS, h2_like_integrals, random_integrals
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "q2c.h")
+
+q2c = pytest.importorskip("paper_2207_03711_amd.q2c", reason="libq2c.so not built")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_0-9]+)\s*\(", src)) - {"sizeof"})
+
+
+def test_header_symbols_are_exported_and_bound():
+    names = _declared_functions()
+    assert "vqe_energy" in names and "mps_apply_gate" in names
+    lib = C.CDLL(q2c.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in q2c.SIGNATURES, n
+
+
+def _host_problem(I):
+    return q2c.vqe_problem_create(None, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+
+
+@pytest.mark.parametrize("which", ["h2", "q8", "q12"])
+def test_pauli_list_matches_oracle(which):
+    if which == "h2":
+        I = h2_like_integrals()
+    elif which == "q8":
+        I = CONFIGS["q8_d16"].integrals()
+    else:
+        I = random_integrals(6, 6, 77)
+    p = _host_problem(I)
+    try:
+        info = q2c.vqe_problem_info(p)
+        x, z, c = q2c.vqe_problem_paulis(p)
+        cid_o, terms_o = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri, I.e_const))
+        assert info["n_strings"] == len(terms_o)
+        assert abs(info["identity_coeff"] - cid_o) < 1e-12
+        assert [(int(a), int(b)) for a, b in zip(x, z)] == [(t[0], t[1]) for t in terms_o]
+        assert np.max(np.abs(c - np.array([t[2] for t in terms_o]))) < 1e-12
+    finally:
+        q2c.vqe_problem_destroy(p)
+
+
+@pytest.mark.parametrize("n_orb,n_elec", [(2, 2), (3, 2), (4, 4)])
+def test_rotations_and_gates_match_oracle(n_orb, n_elec):
+    I = random_integrals(n_orb, n_elec, 5)
+    p = _host_problem(I)
+    try:
+        n = 2 * n_orb
+        info = q2c.vqe_problem_info(p)
+        rots_o, gates_o = uccsd.compile_fused(n, n_elec)
+        assert info["n_params"] == len(uccsd.excitations(n, n_elec))
+        assert info["n_rotations"] == len(rots_o)
+        assert info["n_gates"] == len(gates_o)
+        x, z, c, par = q2c.vqe_problem_rotations(p)
+        for m, r in enumerate(rots_o):
+            assert (int(x[m]), int(z[m]), int(par[m])) == (r.x, r.z, r.param)
+            assert abs(c[m] - r.c) < 1e-15
+        site, rot, pre, post = q2c.vqe_problem_gates(p)
+        for g, go in enumerate(gates_o):
+            assert site[g] == go.site and rot[g] == go.rot
+            if go.rot < 0:
+                assert np.max(np.abs(pre[g] - go.mat)) < 1e-14
+                assert np.max(np.abs(post[g] - np.eye(4))) < 1e-15
+            else:
+                assert np.max(np.abs(pre[g] - go.pre)) < 1e-14
+                assert np.max(np.abs(post[g] - go.post)) < 1e-14
+    finally:
+        q2c.vqe_problem_destroy(p)
+
+
+def test_counts_at_16_qubits():
+    I = CONFIGS["q16_d64"].integrals()
+    p = _host_problem(I)
+    try:
+        info = q2c.vqe_problem_info(p)
+        assert (info["n_params"], info["n_rotations"], info["n_gates"]) == (360, 2688, 55424)
+        cid_o, terms_o = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri))
+        assert info["n_strings"] == len(terms_o)
+    finally:
+        q2c.vqe_problem_destroy(p)
+
+
+def _expect_error(fn, code):
+    with pytest.raises(q2c.Q2CError) as ei:
+        fn()
+    assert ei.value.code == code
+    assert q2c.last_error()
+
+
+def test_argument_errors():
+    I = random_integrals(2, 2, 1)
+    _expect_error(lambda: q2c.vqe_problem_create(None, 0, 0, I.h1, I.eri), q2c.Q2C_ERR_ARG)
+    _expect_error(lambda: q2c.vqe_problem_create(None, 2, 3, I.h1, I.eri), q2c.Q2C_ERR_ARG)
+    _expect_error(lambda: q2c.vqe_problem_create(None, 2, 6, I.h1, I.eri), q2c.Q2C_ERR_ARG)
+    bad = I.eri.copy()
+    bad[0, 1, 0, 1] = np.nan
+    _expect_error(lambda: q2c.vqe_problem_create(None, 2, 2, I.h1, bad), q2c.Q2C_ERR_ARG)
+    badh = I.h1.copy()
+    badh[1, 1] = np.inf
+    _expect_error(lambda: q2c.vqe_problem_create(None, 2, 2, badh, I.eri), q2c.Q2C_ERR_ARG)
+    # NULL handles
+    assert q2c.lib.vqe_problem_destroy(None) == q2c.Q2C_ERR_ARG
+    assert q2c.lib.mps_destroy(None) == q2c.Q2C_ERR_ARG
+    assert q2c.lib.q2c_ctx_destroy(None) == q2c.Q2C_ERR_ARG
+    assert q2c.lib.mps_apply_gate(None, 0, None, None) == q2c.Q2C_ERR_ARG
+    # a host-only problem cannot be evaluated
+    p = _host_problem(I)
+    try:
+        th = np.zeros(q2c.vqe_problem_info(p)["n_params"])
+        _expect_error(lambda: q2c.vqe_energy(p, th, 4), q2c.Q2C_ERR_ARG)
+    finally:
+        q2c.vqe_problem_destroy(p)
+
+
+def test_context_without_gpu_reports_device_error():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    _expect_error(lambda: q2c.q2c_ctx_create(0), q2c.Q2C_ERR_DEVICE)
