@@ -103,7 +103,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="q16_d64", choices=sorted(CONFIGS))
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -114,6 +114,7 @@ def main():
               "(see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("Q2C_PROGRESS", "1")
     import torch
 
     if not torch.cuda.is_available():

@@ -89,6 +89,10 @@ typedef struct {
   double reduce_ms;            /* HIP-event time of the energy reduction                  */
   int gate_launches;           /* gate-kernel launches                                    */
   int n_circuits;              /* circuits (MPS evolutions) run                           */
+  /* Shader-clock cycles spent by the gate kernel in each phase of the update,
+   * summed over gates and circuits: contraction + gate + scaling, LQ, QR,
+   * Jacobi sweeps, back-transformation, truncation + update.                  */
+  double cycles[6];
 } q2c_stats;
 
 /* Context: one device, one HIP stream.

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -249,6 +251,7 @@ void fill_stats(q2c_stats* out, const std::vector<double>& st, int slots, double
     s.max_abs_imag = std::max(s.max_abs_imag, p[q2c::kStatMaxImag]);
     s.gate_flops += p[q2c::kStatFlops];
     s.jacobi_sweeps += p[q2c::kStatSweepSum];
+    for (int c = 0; c < 6; ++c) s.cycles[c] += p[q2c::kStatCycContract + c];
     if (i == 0) s.norm = p[q2c::kStatNorm];
   }
   s.seconds = seconds;
@@ -336,6 +339,11 @@ void run_circuits(vqe_problem* p, int D, const double* theta, int n_slots, const
   hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, d_shift_rot, d_shift_val, st), "angles");
   const q2c::SvdParams sp = svd_params(ctx);
   int launches = 0;
+  static const bool progress = [] {
+    const char* e = std::getenv("Q2C_PROGRESS");
+    return e && *e && *e != '0';
+  }();
+  const auto tp0 = std::chrono::steady_clock::now();
   hip_check(hipEventRecord(ev.e[0], st), "event");
   for (int g0 = 0; g0 < p->dev.n_gates; g0 += kGateChunk) {
     const int g1 = std::min(p->dev.n_gates, g0 + kGateChunk);
@@ -343,6 +351,12 @@ void run_circuits(vqe_problem* p, int D, const double* theta, int n_slots, const
                                 p->dev.n_rot, sp, st),
               "gates");
     ++launches;
+    if (progress) {
+      hip_check(hipStreamSynchronize(st), "sync");
+      std::fprintf(stderr, "[q2c] %d circuit(s): gates %d/%d done, %.1f s\n", n_slots, g1, p->dev.n_gates,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - tp0).count());
+      std::fflush(stderr);
+    }
   }
   hip_check(hipEventRecord(ev.e[1], st), "event");
   hip_check(q2c::launch_envs(db, st), "envs");

@@ -65,7 +65,14 @@ enum {
   kStatMaxImag = 5,
   kStatFlops = 6,
   kStatSweepSum = 7,
-  kNStats = 8
+  // device cycle counters per phase of the gate update (thread 0, summed)
+  kStatCycContract = 8,
+  kStatCycLQ = 9,
+  kStatCycQR = 10,
+  kStatCycJacobi = 11,
+  kStatCycBack = 12,
+  kStatCycUpdate = 13,
+  kNStats = 16
 };
 enum { kFlagNoConv = 1, kFlagNumeric = 2 };
 

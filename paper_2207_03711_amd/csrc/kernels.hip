@@ -163,7 +163,7 @@ __global__ void k_init_product(DevBatch b, const uint8_t* occ) {
   }
   for (int i = threadIdx.x; i <= N; i += blockDim.x) b.chi[slot * (N + 1) + i] = 1;
   for (int n = threadIdx.x; n < N - 1; n += blockDim.x) b.lam[slot * b.lam_stride + b.lam_off[n]] = 1.0;
-  if (threadIdx.x < kNStats) b.stats[slot * kNStats + threadIdx.x] = 0.0;
+  for (int i = threadIdx.x; i < kNStats; i += blockDim.x) b.stats[slot * kNStats + i] = 0.0;
   if (threadIdx.x == 0) {
     b.stats[slot * kNStats + kStatMaxChi] = 1.0;
     b.flags[slot] = 0;
@@ -263,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     double2* Bn1 = v.sites + b.site_off[n + 1];
     const int m = 2 * chil, nn = 2 * chir;
     __syncthreads();
+    long long tc0 = clock64();
 
     // ---- Phase A: Theta = Bn * Bn1 (Eq. 7 before the gate), per j ---------
     for (int j = 0; j < 2; ++j)
@@ -291,6 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     }
     __syncthreads();
 
+    long long tc1 = clock64();
     // ---- Phase B: SVD of A = M' (m x nn), Eq. 9 -----------------------------
     const int r = m < nn ? m : nn;
     // B1: LQ, A <- A H_0 H_1 ... (reflectors on rows, stored in H)
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
       for (int j = k + tid; j < nn; j += blockDim.x) v.A[(long)k * nn + j] = j == k ? sbeta : cmk(0.0, 0.0);
       __syncthreads();
     }
+    long long tc2 = clock64();
     // B2: QR of the m x r lower-trapezoidal L (reflectors on columns)
     for (int k = 0; k < r; ++k) {
       const int L = m - k;
@@ -343,6 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
       for (int i = tid; i < L; i += blockDim.x) v.A[(long)(k + i) * nn + k] = i == 0 ? sbeta : cmk(0.0, 0.0);
       __syncthreads();
     }
+    long long tc3 = clock64();
     // B3: one-sided Jacobi on the rows of the r x r upper triangle
     int sweeps = 0;
     bool converged = r < 2;
@@ -414,6 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
         }
       }
     }
+    long long tc4 = clock64();
     // B4: back-transform rows: [F, 0] H_{r-1} ... H_0 -> s_k w_k^H
     for (int a = wave; a < r; a += nwaves) {
       double2* row = v.A + (long)a * nn;
@@ -436,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     }
     __syncthreads();
 
+    long long tc5 = clock64();
     // ---- Phase C: truncate (Eq. 9), update (Eq. 10) --------------------------
     for (int a = tid; a < r; a += blockDim.x) {
       const double sa = v.S[a];
@@ -500,7 +506,16 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     __syncthreads();
     // B_n = M W^H / ||S_kept||  (Eq. 10, no division by Schmidt values)
     bgemm<false, true>(m, keep, nn, v.M, nn, v.W, nn, Bn, capl_r, cmk(1.0 / nrm, 0.0), false, lds_gemm);
-    if (tid == 0) v.chi[n + 1] = keep;
+    if (tid == 0) {
+      v.chi[n + 1] = keep;
+      const long long tc6 = clock64();
+      v.stats[kStatCycContract] += double(tc1 - tc0);
+      v.stats[kStatCycLQ] += double(tc2 - tc1);
+      v.stats[kStatCycQR] += double(tc3 - tc2);
+      v.stats[kStatCycJacobi] += double(tc4 - tc3);
+      v.stats[kStatCycBack] += double(tc5 - tc4);
+      v.stats[kStatCycUpdate] += double(tc6 - tc5);
+    }
     __syncthreads();
   }
 }

@@ -63,10 +63,15 @@ class q2c_stats(C.Structure):
         ("reduce_ms", C.c_double),
         ("gate_launches", C.c_int),
         ("n_circuits", C.c_int),
+        ("cycles", C.c_double * 6),
     ]
 
+    PHASES = ("contract", "lq", "qr", "jacobi", "back", "update")
+
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "cycles"}
+        d["cycles"] = dict(zip(self.PHASES, list(self.cycles)))
+        return d
 
 
 def _load():
