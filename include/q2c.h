@@ -65,6 +65,10 @@ typedef struct {
                                (0 -> 1e-15)                                               */
   int slots;                /* max circuits resident at once in batched calls (0 -> 256)  */
   size_t hbm_budget_bytes;  /* device memory the context may hold (0 -> 64 GiB)           */
+  int svd_algorithm;        /* 0: Golub-Kahan bidiagonalisation, bisection for the kept
+                               singular values, twisted-factorisation vectors (D <= 64;
+                               falls back to 1 when the vectors cannot be certified);
+                               1: LQ+QR-preconditioned one-sided Jacobi                    */
 } q2c_opts;
 
 /* Statistics of the last state evolution (all over the gates applied). */
@@ -90,9 +94,14 @@ typedef struct {
   int gate_launches;           /* gate-kernel launches                                    */
   int n_circuits;              /* circuits (MPS evolutions) run                           */
   /* Shader-clock cycles spent by the gate kernel in each phase of the update,
-   * summed over gates and circuits: contraction + gate + scaling, LQ, QR,
-   * Jacobi sweeps, back-transformation, truncation + update.                  */
+   * summed over gates and circuits: [0] contraction + gate + scaling,
+   * [1] reduction (bidiagonalisation, or LQ + QR), [2] singular values
+   * (bisection, or Jacobi sweeps), [3] vectors (twisted factorisations +
+   * CholQR2, or row back-transformation), [4] back-transformation of the
+   * kept vectors (or sorting), [5] truncation + update.                      */
   double cycles[6];
+  double svd_bisect_gates;     /* gate SVDs done by bisection                               */
+  double svd_fallbacks;        /* bisection SVDs that fell back to Jacobi                   */
 } q2c_stats;
 
 /* Context: one device, one HIP stream.

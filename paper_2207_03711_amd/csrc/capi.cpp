@@ -199,6 +199,7 @@ struct Batch {
     b.wsA = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
     b.wsH = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
     b.wsW = static_cast<double2*>(alloc(S * b.ws_stride * sizeof(double2)));
+    b.wsV = static_cast<double2*>(alloc(S * 4 * b.ws_stride * sizeof(double2)));
     b.wsS = static_cast<double*>(alloc(S * 2 * b.ws * sizeof(double)));
     b.wsP = static_cast<int*>(alloc(S * b.ws * sizeof(int)));
     b.envL = static_cast<double2*>(alloc(S * b.env_stride * sizeof(double2)));
@@ -214,6 +215,7 @@ q2c::SvdParams svd_params(const q2c_ctx* ctx) {
   sp.max_sweeps = ctx->opts.max_sweeps;
   sp.tol = ctx->opts.svd_tol;
   sp.cutoff_rel = ctx->opts.sv_cutoff_rel;
+  sp.algo = ctx->opts.svd_algorithm;
   return sp;
 }
 
@@ -252,6 +254,8 @@ void fill_stats(q2c_stats* out, const std::vector<double>& st, int slots, double
     s.gate_flops += p[q2c::kStatFlops];
     s.jacobi_sweeps += p[q2c::kStatSweepSum];
     for (int c = 0; c < 6; ++c) s.cycles[c] += p[q2c::kStatCycContract + c];
+    s.svd_bisect_gates += p[q2c::kStatBisect];
+    s.svd_fallbacks += p[q2c::kStatFallbacks];
     if (i == 0) s.norm = p[q2c::kStatNorm];
   }
   s.seconds = seconds;
@@ -447,6 +451,7 @@ int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx**
     if (o.slots <= 0) o.slots = 256;
     if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = size_t(64) << 30;
     require(o.sv_cutoff_rel < 1.0 && o.svd_tol < 1e-3, "bad tolerances");
+    require(o.svd_algorithm == 0 || o.svd_algorithm == 1, "svd_algorithm must be 0 or 1");
     c->opts = o;
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);

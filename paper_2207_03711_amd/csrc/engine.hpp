@@ -48,6 +48,7 @@ struct DevBatch {
   double2* wsA = nullptr;     // [slot][ws*ws] M' -> Jacobi rows
   double2* wsH = nullptr;     // [slot][ws*ws] LQ reflectors
   double2* wsW = nullptr;     // [slot][ws*ws] sorted normalised rows (W^H)
+  double2* wsV = nullptr;     // [slot][4*ws*ws] vector scratch of the bisection SVD
   double* wsS = nullptr;      // [slot][2*ws] row norms
   int* wsP = nullptr;         // [slot][ws] sort permutation
   double2* envL = nullptr;    // [slot][env_stride]
@@ -72,6 +73,8 @@ enum {
   kStatCycJacobi = 11,
   kStatCycBack = 12,
   kStatCycUpdate = 13,
+  kStatFallbacks = 14,  // bisection SVDs that fell back to Jacobi
+  kStatBisect = 15,     // gates whose SVD used bisection
   kNStats = 16
 };
 enum { kFlagNoConv = 1, kFlagNumeric = 2 };
@@ -80,6 +83,7 @@ struct SvdParams {
   int max_sweeps;
   double tol;
   double cutoff_rel;
+  int algo;  // 0: bidiagonal bisection with Jacobi fallback; 1: Jacobi only
 };
 
 // Launchers (stream-ordered, asynchronous).

@@ -187,6 +187,7 @@ struct SlotView {
   double* lam;
   int* chi;
   double2 *M, *A, *H, *W;
+  double* V;  // inverse-iteration scratch and real vectors (8 ws^2 doubles)
   double* S;
   int* P;
   double* stats;
@@ -202,6 +203,7 @@ __device__ SlotView slot_view(const DevBatch& b, int slot) {
   v.A = b.wsA + slot * b.ws_stride;
   v.H = b.wsH + slot * b.ws_stride;
   v.W = b.wsW + slot * b.ws_stride;
+  v.V = reinterpret_cast<double*>(b.wsV + slot * 4 * b.ws_stride);
   v.S = b.wsS + slot * 2 * b.ws;
   v.P = b.wsP + slot * b.ws;
   v.stats = b.stats + slot * kNStats;
@@ -214,35 +216,658 @@ __device__ __forceinline__ int rr_row(int pos, int t, int P) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + t) % (P - 1));
 }
 
-constexpr int kMaxPerLane = 8;  // row length <= 512
+constexpr int kMaxPerLane = 8;  // Jacobi row length <= 512
+constexpr int kQB = 128;        // bisection path: q = min(m, n) <= kQB
+constexpr int kKB = 64;         // bisection path: kept vectors <= kKB
+
+// Static LDS of the gate kernel (about 100 KB of the 160 KB per CU).
+struct GateLds {
+  double2 gemm[2 * 64 * 8];
+  double2 O[16];
+  double2 uq[512], wq[512], vq[512], zq[512];
+  double2 dc[kQB], ec[kQB], pa[kQB], pb[kQB];  // bidiagonal and its phases
+  double t[2 * kQB], t2[2 * kQB];               // Golub-Kahan tridiagonal
+  double sig[512];                              // kept singular values, descending
+  double G[kKB * kKB];                          // Gram / Cholesky factor
+  int blo[2 * kQB], bhi[2 * kQB];               // blocks of the split tridiagonal
+  double red[16];
+  double2 sbeta;
+  int szero, srot, sabort, skeep, sfail, snblk;
+  double sdisc, stot, snorm, sgersh, stmax;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal with zero
+// diagonal and squared off-diagonals t2[b0 .. b1-2] (indices b0 .. b1-1):
+// LDL^T Sturm count with tiny pivots replaced by -pivmin.
+__device__ int tgk_count(const double* t2, int b0, int b1, double x, double pivmin) {
+  double q = -x;
+  int c = q < 0.0 ? 1 : 0;
+  for (int i = b0; i < b1 - 1; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = -x - t2[i] / q;
+    c += q < 0.0 ? 1 : 0;
+  }
+  return c;
+}
+
+// ---- Phase A: Theta = B_n B_{n+1}, gate mixing (Eq. 7), lambda scaling (Eq. 8)
+__device__ void gate_contract(const DevBatch& b, SlotView& v, GateLds& L, int n, int chil, int chim, int chir) {
+  const int tid = threadIdx.x;
+  const int nn = 2 * chir, m = 2 * chil;
+  const int capl_r = b.cap[n + 1], capr_r = b.cap[n + 2];
+  const double2* Bn = v.sites + b.site_off[n];
+  const double2* Bn1 = v.sites + b.site_off[n + 1];
+  for (int j = 0; j < 2; ++j)
+    bgemm<false, false>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, v.M + j * chir, nn,
+                        cmk(1.0, 0.0), false, L.gemm);
+  double part = 0.0;
+  for (int idx = tid; idx < chil * chir; idx += blockDim.x) {
+    const int a = idx / chir, c = idx - a * chir;
+    double2 t[4];
+#pragma unroll
+    for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+      for (int jp = 0; jp < 2; ++jp) t[2 * ip + jp] = v.M[(long)(2 * a + ip) * nn + jp * chir + c];
+    const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + a];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        double2 s = cmk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cfma(s, L.O[(2 * i + jj) * 4 + q], t[q]);
+        const long off = (long)(2 * a + i) * nn + jj * chir + c;
+        v.M[off] = s;
+        const double2 sp = cscale(s, la);
+        v.A[off] = sp;
+        part += cabs2(sp);
+      }
+  }
+  const double tot = block_sum(part, L.red);
+  if (tid == 0) L.stot = tot;
+  __syncthreads();
+}
+
+// M' = lambda * M again (the bisection path overwrites A).
+__device__ void restore_mprime(const DevBatch& b, SlotView& v, int n, int chil, int chir) {
+  const int nn = 2 * chir;
+  for (int idx = threadIdx.x; idx < 2 * chil * nn; idx += blockDim.x) {
+    const int row = idx / nn;
+    const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + (row >> 1)];
+    v.A[idx] = cscale(v.M[idx], la);
+  }
+  __syncthreads();
+}
+
+// ---- Phase B (default): SVD by Golub-Kahan bidiagonalisation, bisection on
+// the Golub-Kahan tridiagonal for the kept singular values, twisted
+// factorisations for their vectors, CholQR2 and back-transformation.
+// Output: L.sig[0..keep) descending, v.W rows = kept rows of W^H (n wide),
+// L.sdisc.  Returns keep, or -1 if the vectors could not be certified (the
+// caller then uses the Jacobi path).  Requires min(m, n) <= kQB, D <= kKB.
+__device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double cutoff, long long* tcyc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const bool trans = m < nn;
+  const int p = trans ? nn : m, q = trans ? m : nn;
+  double2* X = trans ? v.H : v.A;
+  const int ldx = q;
+  if (trans) {
+    // X = A^H, p = nn rows, q = m columns
+    for (int idx = tid; idx < p * q; idx += blockDim.x) {
+      const int i = idx / q, j = idx - i * q;
+      X[idx] = cconj(v.A[(long)j * nn + i]);
+    }
+    __syncthreads();
+  }
+  // -- Golub-Kahan: H_k from the left on column k, G_k from the right on row k
+  for (int k = 0; k < q; ++k) {
+    const int Lc = p - k;
+    for (int i = tid; i < Lc; i += blockDim.x) L.uq[i] = X[(long)(k + i) * ldx + k];
+    __syncthreads();
+    if (wave == 0) {
+      bool z;
+      wave_householder(L.uq, Lc, false, L.uq, &L.sbeta, &z);
+      if (lane == 0) L.szero = z;
+    }
+    __syncthreads();
+    if (tid == 0) L.dc[k] = L.sbeta;
+    const int nw = q - k - 1;
+    if (!L.szero && nw > 0) {
+      // w_j = sum_i conj(u_i) X[k+i][k+1+j]: 4 row groups x up to 128 columns per pass
+      for (int j0 = 0; j0 < nw; j0 += 128) {
+        const int jj = j0 + (tid & 127), g = tid >> 7;
+        double wr = 0.0, wi = 0.0;
+        if (jj < nw) {
+          for (int i = g; i < Lc; i += 4) {
+            const double2 pr = cmul(cconj(L.uq[i]), X[(long)(k + i) * ldx + k + 1 + jj]);
+            wr += pr.x;
+            wi += pr.y;
+          }
+        }
+        L.zq[tid] = cmk(wr, wi);
+        __syncthreads();
+        if (tid < 128 && j0 + tid < nw)
+          L.wq[j0 + tid] = cadd(cadd(L.zq[tid], L.zq[tid + 128]), cadd(L.zq[tid + 256], L.zq[tid + 384]));
+        __syncthreads();
+      }
+      for (int idx = tid; idx < Lc * nw; idx += blockDim.x) {
+        const int i = idx / nw, jj = idx - i * nw;
+        double2* e = &X[(long)(k + i) * ldx + k + 1 + jj];
+        *e = csub(*e, cmul(L.uq[i], L.wq[jj]));
+      }
+    }
+    for (int i = tid; i < Lc; i += blockDim.x) X[(long)(k + i) * ldx + k] = L.uq[i];  // left reflector
+    __syncthreads();
+    if (nw > 0) {
+      if (wave == 0) {
+        bool z;
+        wave_householder(X + (long)k * ldx + k + 1, nw, true, L.vq, &L.sbeta, &z);
+        if (lane == 0) L.szero = z;
+      }
+      __syncthreads();
+      if (tid == 0) L.ec[k] = L.sbeta;
+      const int nr = p - k - 1;
+      if (!L.szero && nr > 0) {
+        // z_i = sum_j X[k+1+i][k+1+j] v_j, 4 lanes per row
+        for (int i0 = 0; i0 < nr; i0 += 128) {
+          const int ii = i0 + (tid >> 2), s4 = tid & 3;
+          double zr = 0.0, zi = 0.0;
+          if (ii < nr) {
+            for (int j = s4; j < nw; j += 4) {
+              const double2 pr = cmul(X[(long)(k + 1 + ii) * ldx + k + 1 + j], L.vq[j]);
+              zr += pr.x;
+              zi += pr.y;
+            }
+          }
+          zr += __shfl_xor(zr, 1, 64);
+          zi += __shfl_xor(zi, 1, 64);
+          zr += __shfl_xor(zr, 2, 64);
+          zi += __shfl_xor(zi, 2, 64);
+          if (s4 == 0 && ii < nr) L.zq[ii] = cmk(zr, zi);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nr * nw; idx += blockDim.x) {
+          const int i = idx / nw, j = idx - i * nw;
+          double2* e = &X[(long)(k + 1 + i) * ldx + k + 1 + j];
+          *e = csub(*e, cmul(L.zq[i], cconj(L.vq[j])));
+        }
+      }
+      for (int j = tid; j < nw; j += blockDim.x) X[(long)k * ldx + k + 1 + j] = L.vq[j];  // right reflector
+      __syncthreads();
+    }
+  }
+  tcyc[0] = clock64();
+  // -- real bidiagonal by diagonal phase scaling; Golub-Kahan tridiagonal t
+  if (tid == 0) {
+    double2 bk = cmk(1.0, 0.0);
+    double tmax = 0.0;
+    for (int k = 0; k < q; ++k) {
+      const double2 d = L.dc[k];
+      const double ad = sqrt(cabs2(d));
+      const double2 ak = ad > 0.0 ? cscale(cmul(d, bk), 1.0 / ad) : bk;
+      L.pa[k] = ak;
+      L.pb[k] = bk;
+      L.t[2 * k] = ad;
+      tmax = fmax(tmax, ad);
+      if (k + 1 < q) {
+        const double2 e = L.ec[k];
+        const double ae = sqrt(cabs2(e));
+        bk = ae > 0.0 ? cscale(cmul(ak, cconj(e)), 1.0 / ae) : cmk(1.0, 0.0);
+        L.t[2 * k + 1] = ae;
+        tmax = fmax(tmax, ae);
+      }
+    }
+    const int nt = 2 * q - 1;
+    double gersh = 0.0;
+    int nb = 0, start = 0;
+    for (int i = 0; i < nt; ++i) {
+      if (L.t[i] <= 1e-15 * tmax) L.t[i] = 0.0;  // split at negligible entries
+      L.t2[i] = L.t[i] * L.t[i];
+      gersh = fmax(gersh, L.t[i] + (i > 0 ? L.t[i - 1] : 0.0));
+      if (L.t[i] == 0.0) {
+        L.blo[nb] = start;
+        L.bhi[nb] = i + 1;
+        ++nb;
+        start = i + 1;
+      }
+    }
+    gersh = fmax(gersh, L.t[nt - 1]);
+    L.blo[nb] = start;
+    L.bhi[nb] = 2 * q;
+    ++nb;
+    L.snblk = nb;
+    L.sgersh = gersh;
+    L.stmax = tmax;
+  }
+  __syncthreads();
+  const int nT = 2 * q;
+  const double pivmin = 2.3e-308 * fmax(1.0, L.stmax * L.stmax);
+  const int kk = D < q ? D : q;
+  // -- bisection: 4 lanes per value, 5-section, 24 steps (interval / 5^24)
+  if (tid < 4 * kKB) {
+    const int j0 = tid >> 2, s4 = tid & 3;
+    const int j = j0 < kk ? j0 : kk - 1;
+    const int idx = nT - 1 - j;  // the value has exactly idx eigenvalues below it
+    double lo = 0.0, hi = L.sgersh * (1.0 + 1e-14) + 1e-300;
+    const int base = lane & ~3;
+    for (int it = 0; it < 24; ++it) {
+      const double w = (hi - lo) * 0.2;
+      const double x = lo + (s4 + 1) * w;
+      const int c = tgk_count(L.t2, 0, nT, x, pivmin);
+      double nlo = lo, nhi = hi;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int cs = __shfl(c, base + s, 64);
+        const double xs = lo + (s + 1) * w;
+        if (cs <= idx) nlo = fmax(nlo, xs);
+        else nhi = fmin(nhi, xs);
+      }
+      lo = nlo;
+      hi = nhi;
+    }
+    if (s4 == 0 && j0 < kk) L.sig[j0] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int keep = -1;
+    const double s0 = L.sig[0];
+    if (s0 > 0.0 && isfinite(s0)) {
+      const int nz = nT - tgk_count(L.t2, 0, nT, cutoff * s0, pivmin);
+      keep = nz < kk ? nz : kk;
+      if (keep < 1) keep = 1;
+      double kept = 0.0;
+      for (int j = 0; j < keep; ++j) kept += L.sig[j] * L.sig[j];
+      L.sdisc = fmax(0.0, L.stot - kept);
+    }
+    L.skeep = keep;
+    L.sfail = 0;
+  }
+  __syncthreads();
+  tcyc[1] = clock64();
+  const int keep = L.skeep;
+  if (keep < 0) return -1;
+  // -- vectors: one lane per kept value, spread over 4 waves
+  // scratch layout (5 q kk <= 5 ws^2 doubles of the 8 ws^2 available)
+  const int KV = kk;
+  double* Dp = v.V;                    // [2q][KV]: D+ pivots, then the vector
+  double* Dm = v.V + (long)nT * KV;    // [2q][KV]: D- pivots
+  double* Y = v.V + 2L * nT * KV;      // [q][KV]: real vectors
+  if (tid < 4 * kKB) {
+    const int j = (tid & 63) * 4 + (tid >> 6);
+    if (j < keep) {
+      const double sj = L.sig[j];
+      const double tol = 1e-13 * L.sig[0];
+      int inst = 0;
+      for (int jp = 0; jp < j; ++jp) inst += fabs(L.sig[jp] - sj) <= tol ? 1 : 0;
+      int b0 = L.blo[0], b1 = L.bhi[0], seen = 0;
+      bool found = false;
+      for (int bk = 0; bk < L.snblk && !found; ++bk) {
+        const int mult = tgk_count(L.t2, L.blo[bk], L.bhi[bk], sj + tol, pivmin) -
+                         tgk_count(L.t2, L.blo[bk], L.bhi[bk], sj - tol, pivmin);
+        if (mult > 0 && seen + mult > inst) {
+          b0 = L.blo[bk];
+          b1 = L.bhi[bk];
+          found = true;
+        }
+        seen += mult;
+      }
+      double nrm2 = 0.0;
+      for (int i = 0; i < nT; ++i) Dp[i * KV + j] = 0.0;
+      if (b1 - b0 == 1) {
+        Dp[b0 * KV + j] = 1.0;
+        nrm2 = 1.0;
+      } else {
+        // forward D+ and backward D- pivots of (T - s I) on the block
+        double dd = -sj;
+        Dp[b0 * KV + j] = dd;
+        for (int i = b0 + 1; i < b1; ++i) {
+          if (fabs(dd) < pivmin) dd = -pivmin;
+          dd = -sj - L.t2[i - 1] / dd;
+          Dp[i * KV + j] = dd;
+        }
+        dd = -sj;
+        Dm[(b1 - 1) * KV + j] = dd;
+        for (int i = b1 - 2; i >= b0; --i) {
+          if (fabs(dd) < pivmin) dd = -pivmin;
+          dd = -sj - L.t2[i] / dd;
+          Dm[i * KV + j] = dd;
+        }
+        int r = b0;
+        double gmin = 1e308;
+        for (int i = b0; i < b1; ++i) {
+          const double g = fabs(Dp[i * KV + j] + Dm[i * KV + j] + sj);
+          if (g < gmin) {
+            gmin = g;
+            r = i;
+          }
+        }
+        // twisted solve: z_r = 1, up with L+, down with U-
+        double z = 1.0;
+        nrm2 = 1.0;
+        for (int i = r - 1; i >= b0; --i) {
+          double dpi = Dp[i * KV + j];
+          if (fabs(dpi) < pivmin) dpi = -pivmin;
+          z = -(L.t[i] / dpi) * z;
+          Dp[i * KV + j] = z;
+          nrm2 += z * z;
+        }
+        Dp[r * KV + j] = 1.0;
+        z = 1.0;
+        for (int i = r + 1; i < b1; ++i) {
+          double dmi = Dm[i * KV + j];
+          if (fabs(dmi) < pivmin) dmi = -pivmin;
+          z = -(L.t[i - 1] / dmi) * z;
+          Dp[i * KV + j] = z;
+          nrm2 += z * z;
+        }
+      }
+      const double inv = 1.0 / sqrt(nrm2);
+      const int off = trans ? 1 : 0;  // X = A: right vectors (even); X = A^H: left vectors (odd)
+      for (int k = 0; k < q; ++k) Y[k * KV + j] = Dp[(2 * k + off) * KV + j] * inv;
+    }
+  }
+  __syncthreads();
+  // -- CholQR2 on Y (q x keep)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int idx = tid; idx < keep * keep; idx += blockDim.x) {
+      const int a = idx / keep, c = idx - a * keep;
+      if (c > a) continue;
+      double s = 0.0;
+      for (int k = 0; k < q; ++k) s += Y[k * KV + a] * Y[k * KV + c];
+      L.G[a * kKB + c] = s;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      bool ok = true;
+      for (int j = 0; j < keep; ++j) {
+        const double djj = L.G[j * kKB + j];
+        if (!(djj > 1e-10) || !isfinite(djj)) ok = false;
+        const double ljj = sqrt(fmax(djj, 1e-300));
+        wave_sync();
+        for (int a = j + 1 + lane; a < keep; a += 64) L.G[a * kKB + j] /= ljj;
+        if (lane == 0) L.G[j * kKB + j] = ljj;
+        wave_sync();
+        for (int a = j + 1 + lane; a < keep; a += 64) {
+          const double laj = L.G[a * kKB + j];
+          for (int c = j + 1; c <= a; ++c) L.G[a * kKB + c] -= laj * L.G[c * kKB + j];
+        }
+        wave_sync();
+      }
+      if (lane == 0) L.sfail = ok ? 0 : 1;
+    }
+    __syncthreads();
+    if (L.sfail) return -1;
+    // Y <- Y L^{-T}, row by row
+    for (int k = tid; k < q; k += blockDim.x) {
+      for (int c = 0; c < keep; ++c) {
+        double s = Y[k * KV + c];
+        for (int e = 0; e < c; ++e) s -= Y[k * KV + e] * L.G[c * kKB + e];
+        Y[k * KV + c] = s / L.G[c * kKB + c];
+      }
+    }
+    __syncthreads();
+  }
+  tcyc[2] = clock64();
+  // -- complex vectors of the bidiagonal, then through the reflectors
+  double2* Wt = v.W;  // [keep][nn]
+  for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
+    const int j = idx / nn, k = idx - j * nn;
+    double2 w = cmk(0.0, 0.0);
+    if (k < q) w = cscale(trans ? L.pa[k] : L.pb[k], Y[k * KV + j]);
+    Wt[idx] = w;
+  }
+  __syncthreads();
+  for (int j = wave; j < keep; j += nwaves) {
+    double2* w = Wt + (long)j * nn;
+    if (!trans) {
+      for (int k = q - 2; k >= 0; --k) {
+        const double2* u = X + (long)k * ldx + k + 1;
+        const int len = q - k - 1;
+        double dr = 0.0, di = 0.0;
+        for (int i = lane; i < len; i += 64) {
+          const double2 pr = cmul(cconj(u[i]), w[k + 1 + i]);
+          dr += pr.x;
+          di += pr.y;
+        }
+        const double2 dot = cmk(wave_sum(dr), wave_sum(di));
+        for (int i = lane; i < len; i += 64) w[k + 1 + i] = csub(w[k + 1 + i], cmul(u[i], dot));
+      }
+    } else {
+      for (int k = q - 1; k >= 0; --k) {
+        const int len = p - k;
+        double dr = 0.0, di = 0.0;
+        for (int i = lane; i < len; i += 64) {
+          const double2 pr = cmul(cconj(X[(long)(k + i) * ldx + k]), w[k + i]);
+          dr += pr.x;
+          di += pr.y;
+        }
+        const double2 dot = cmk(wave_sum(dr), wave_sum(di));
+        for (int i = lane; i < len; i += 64) w[k + i] = csub(w[k + i], cmul(X[(long)(k + i) * ldx + k], dot));
+      }
+    }
+    for (int i = lane; i < nn; i += 64) w[i] = cconj(w[i]);  // rows of W^H
+  }
+  __syncthreads();
+  return keep;
+}
+
+// ---- Phase B (fallback): LQ + QR preconditioning and one-sided row Jacobi.
+// Same outputs as svd_bisect.  *sweeps_out / *conv_out report convergence.
+__device__ int svd_jacobi(const DevBatch& b, SlotView& v, GateLds& L, int m, int nn, SvdParams sp, int* sweeps_out,
+                          bool* conv_out, long long* tcyc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int r = m < nn ? m : nn;
+  // LQ: A <- A H_0 H_1 ... (reflectors on rows, stored in H)
+  for (int k = 0; k < r; ++k) {
+    if (wave == 0) {
+      bool z;
+      wave_householder(v.A + (long)k * nn + k, nn - k, true, v.H + (long)k * nn + k, &L.sbeta, &z);
+      if (lane == 0) L.szero = z;
+    }
+    __syncthreads();
+    if (!L.szero) {
+      for (int a = k + 1 + wave; a < m; a += nwaves) {
+        double2* row = v.A + (long)a * nn;
+        const double2* u = v.H + (long)k * nn;
+        double wr = 0.0, wi = 0.0;
+        for (int j = k + lane; j < nn; j += 64) {
+          const double2 pr = cmul(row[j], u[j]);
+          wr += pr.x;
+          wi += pr.y;
+        }
+        const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+        for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
+      }
+    }
+    for (int j = k + tid; j < nn; j += blockDim.x) v.A[(long)k * nn + j] = j == k ? L.sbeta : cmk(0.0, 0.0);
+    __syncthreads();
+  }
+  // QR of the m x r lower-trapezoidal L (reflectors on columns)
+  for (int k = 0; k < r; ++k) {
+    const int Lc = m - k;
+    for (int i = tid; i < Lc; i += blockDim.x) L.uq[i] = v.A[(long)(k + i) * nn + k];
+    __syncthreads();
+    if (wave == 0) {
+      bool z;
+      wave_householder(L.uq, Lc, false, L.uq, &L.sbeta, &z);
+      if (lane == 0) L.szero = z;
+    }
+    __syncthreads();
+    if (!L.szero) {
+      for (int c = k + 1 + wave; c < r; c += nwaves) {
+        double wr = 0.0, wi = 0.0;
+        for (int i = lane; i < Lc; i += 64) {
+          const double2 pr = cmul(cconj(L.uq[i]), v.A[(long)(k + i) * nn + c]);
+          wr += pr.x;
+          wi += pr.y;
+        }
+        const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+        for (int i = lane; i < Lc; i += 64) {
+          double2* e = &v.A[(long)(k + i) * nn + c];
+          *e = csub(*e, cmul(L.uq[i], w));
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < Lc; i += blockDim.x) v.A[(long)(k + i) * nn + k] = i == 0 ? L.sbeta : cmk(0.0, 0.0);
+    __syncthreads();
+  }
+  tcyc[0] = clock64();
+  // one-sided Jacobi on the rows of the r x r upper triangle
+  int sweeps = 0;
+  bool converged = r < 2;
+  if (r >= 2) {
+    const int Pe = r + (r & 1);
+    for (int sw = 0; sw < sp.max_sweeps; ++sw) {
+      if (tid == 0) L.srot = 0;
+      __syncthreads();
+      for (int t = 0; t < Pe - 1; ++t) {
+        for (int kp = wave; kp < Pe / 2; kp += nwaves) {
+          const int pr_ = rr_row(kp, t, Pe), qr_ = rr_row(Pe - 1 - kp, t, Pe);
+          if (pr_ >= r || qr_ >= r) continue;
+          double2* rp = v.A + (long)pr_ * nn;
+          double2* rq = v.A + (long)qr_ * nn;
+          double2 xp[kMaxPerLane], xq[kMaxPerLane];
+          double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+          for (int e = 0; e < kMaxPerLane; ++e) {
+            const int j = lane + 64 * e;
+            if (j < r) {
+              xp[e] = rp[j];
+              xq[e] = rq[j];
+            } else {
+              xp[e] = cmk(0.0, 0.0);
+              xq[e] = cmk(0.0, 0.0);
+            }
+            al += cabs2(xp[e]);
+            be += cabs2(xq[e]);
+            gr += xp[e].x * xq[e].x + xp[e].y * xq[e].y;
+            gi += xp[e].y * xq[e].x - xp[e].x * xq[e].y;
+          }
+          al = wave_sum(al);
+          be = wave_sum(be);
+          gr = wave_sum(gr);
+          gi = wave_sum(gi);
+          const double ag = sqrt(gr * gr + gi * gi);
+          if (!(al > 0.0 && be > 0.0) || !(ag > sp.tol * sqrt(al) * sqrt(be))) continue;
+          const double zeta = (be - al) / (2.0 * ag);
+          double tt;
+          if (fabs(zeta) > 1e150)
+            tt = 0.5 / zeta;
+          else
+            tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          const double2 s_ip = cscale(cmk(gr / ag, gi / ag), sn);
+          const double2 s_im = cconj(s_ip);
+#pragma unroll
+          for (int e = 0; e < kMaxPerLane; ++e) {
+            const int j = lane + 64 * e;
+            if (j < r) {
+              rp[j] = csub(cscale(xp[e], cs), cmul(s_ip, xq[e]));
+              rq[j] = cadd(cmul(s_im, xp[e]), cscale(xq[e], cs));
+            }
+          }
+          if (lane == 0) L.srot = 1;
+        }
+        __syncthreads();
+      }
+      sweeps = sw + 1;
+      const int any = L.srot;
+      __syncthreads();
+      if (!any) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  *sweeps_out = sweeps;
+  *conv_out = converged;
+  tcyc[1] = clock64();
+  // back-transform rows: [F, 0] H_{r-1} ... H_0 -> s_k w_k^H; row norms
+  for (int a = wave; a < r; a += nwaves) {
+    double2* row = v.A + (long)a * nn;
+    for (int j = r + lane; j < nn; j += 64) row[j] = cmk(0.0, 0.0);
+    for (int k = r - 1; k >= 0; --k) {
+      const double2* u = v.H + (long)k * nn;
+      double wr = 0.0, wi = 0.0;
+      for (int j = k + lane; j < nn; j += 64) {
+        const double2 pr = cmul(row[j], u[j]);
+        wr += pr.x;
+        wi += pr.y;
+      }
+      const double2 w = cmk(wave_sum(wr), wave_sum(wi));
+      for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
+    }
+    double s2 = 0.0;
+    for (int j = lane; j < nn; j += 64) s2 += cabs2(row[j]);
+    s2 = wave_sum(s2);
+    if (lane == 0) v.S[a] = sqrt(s2);
+  }
+  __syncthreads();
+  tcyc[2] = clock64();
+  // sort descending (ties by index), truncate, normalised rows -> W
+  for (int a = tid; a < r; a += blockDim.x) {
+    const double sa = v.S[a];
+    int rank = 0;
+    for (int qq = 0; qq < r; ++qq) {
+      const double sq = v.S[qq];
+      rank += (sq > sa || (sq == sa && qq < a)) ? 1 : 0;
+    }
+    v.P[rank] = a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int keep = -1;
+    const double s1 = v.S[v.P[0]];
+    if (s1 > 0.0 && isfinite(s1)) {
+      int nz = 0;
+      for (int qq = 0; qq < r; ++qq) nz += v.S[qq] > sp.cutoff_rel * s1 ? 1 : 0;
+      keep = nz < b.max_bond ? nz : b.max_bond;
+      double disc = 0.0;
+      for (int qq = keep; qq < r; ++qq) {
+        const double s = v.S[v.P[qq]];
+        disc += s * s;
+      }
+      L.sdisc = disc;
+      for (int qq = 0; qq < keep; ++qq) L.sig[qq] = v.S[v.P[qq]];
+    }
+    L.skeep = keep;
+  }
+  __syncthreads();
+  const int keep = L.skeep;
+  for (int idx = tid; keep > 0 && idx < keep * nn; idx += blockDim.x) {
+    const int k = idx / nn, col = idx - k * nn;
+    const int src = v.P[k];
+    v.W[idx] = cscale(v.A[(long)src * nn + col], 1.0 / v.S[src]);
+  }
+  __syncthreads();
+  return keep;
+}
 
 __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restrict__ gsite,
                                                   const int* __restrict__ grot, const double2* __restrict__ gpre,
                                                   const double2* __restrict__ gpost, const double* __restrict__ phi_all,
                                                   int n_rot, int g0, int g1, SvdParams sp) {
-  __shared__ double2 lds_gemm[2 * 64 * 8];
-  __shared__ double2 O[16];
-  __shared__ double2 uq[512];  // column reflector (length <= 2 * max bond)
-  __shared__ double red[kBlock / 64];
-  __shared__ double2 sbeta;
-  __shared__ bool szero;
-  __shared__ int srot;
-  __shared__ int sabort;
-
+  __shared__ GateLds L;
   const int slot = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int tid = threadIdx.x;
   SlotView v = slot_view(b, slot);
   const double* phi = phi_all ? phi_all + (long)slot * n_rot : nullptr;
-  if (tid == 0) sabort = (*v.flags & kFlagNumeric) ? 1 : 0;
+  if (tid == 0) L.sabort = (*v.flags & kFlagNumeric) ? 1 : 0;
   __syncthreads();
-  if (sabort) return;
+  if (L.sabort) return;
 
   for (int g = g0; g < g1; ++g) {
     const int n = gsite[g];
     const int rot = grot[g];
     if (tid < 16) {
       if (rot < 0) {
-        O[tid] = gpre[(long)g * 16 + tid];
+        L.O[tid] = gpre[(long)g * 16 + tid];
       } else {
         const double ph = phi[rot];
         const double2 dm = cmk(cos(0.5 * ph), -sin(0.5 * ph));  // exp(-i phi/2)
@@ -253,268 +878,84 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
           const double2 d = (k & 1) ? dp : dm;
           cfma(s, cmul(gpost[(long)g * 16 + i * 4 + k], d), gpre[(long)g * 16 + k * 4 + j]);
         }
-        O[tid] = s;
+        L.O[tid] = s;
       }
     }
     const int chil = v.chi[n], chim = v.chi[n + 1], chir = v.chi[n + 2];
-    const int capl_r = b.cap[n + 1];   // capacity of bond n (right bond of site n)
-    const int capr_r = b.cap[n + 2];   // capacity of bond n+1
+    const int m = 2 * chil, nn = 2 * chir;
+    const int qmin = m < nn ? m : nn;
+    __syncthreads();
+    long long tc[8];
+    tc[0] = clock64();
+    gate_contract(b, v, L, n, chil, chim, chir);
+    tc[1] = clock64();
+
+    int keep = -1, sweeps = 0;
+    bool conv = true, used_bisect = false, fell_back = false;
+    long long tb[3] = {tc[1], tc[1], tc[1]};
+    if (sp.algo == 0 && qmin <= kQB && b.max_bond <= kKB) {
+      used_bisect = true;
+      keep = svd_bisect(v, L, m, nn, b.max_bond, sp.cutoff_rel, tb);
+      if (keep < 0) {
+        fell_back = true;
+        restore_mprime(b, v, n, chil, chir);
+      }
+    }
+    if (keep < 0) keep = svd_jacobi(b, v, L, m, nn, sp, &sweeps, &conv, tb);
+    tc[2] = tb[0];
+    tc[3] = tb[1];
+    tc[4] = tb[2];
+    tc[5] = clock64();
+    if (tid == 0 && keep < 1) {
+      *v.flags |= kFlagNumeric;
+      L.sabort = 1;
+    }
+    __syncthreads();
+    if (L.sabort) return;
+
+    // ---- Phase C: truncate (Eq. 9), update (Eq. 10)
+    const int capl_r = b.cap[n + 1], capr_r = b.cap[n + 2];
     double2* Bn = v.sites + b.site_off[n];
     double2* Bn1 = v.sites + b.site_off[n + 1];
-    const int m = 2 * chil, nn = 2 * chir;
-    __syncthreads();
-    long long tc0 = clock64();
-
-    // ---- Phase A: Theta = Bn * Bn1 (Eq. 7 before the gate), per j ---------
-    for (int j = 0; j < 2; ++j)
-      bgemm<false, false>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, v.M + j * chir, nn,
-                          cmk(1.0, 0.0), false, lds_gemm);
-    // gate mixing (Eq. 7) and lambda scaling (Eq. 8)
-    for (int idx = tid; idx < chil * chir; idx += blockDim.x) {
-      const int a = idx / chir, c = idx - a * chir;
-      double2 t[4];
-#pragma unroll
-      for (int ip = 0; ip < 2; ++ip)
-#pragma unroll
-        for (int jp = 0; jp < 2; ++jp) t[2 * ip + jp] = v.M[(long)(2 * a + ip) * nn + jp * chir + c];
-      const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + a];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          double2 s = cmk(0.0, 0.0);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) cfma(s, O[(2 * i + jj) * 4 + q], t[q]);
-          const long off = (long)(2 * a + i) * nn + jj * chir + c;
-          v.M[off] = s;
-          v.A[off] = cscale(s, la);
-        }
-    }
-    __syncthreads();
-
-    long long tc1 = clock64();
-    // ---- Phase B: SVD of A = M' (m x nn), Eq. 9 -----------------------------
-    const int r = m < nn ? m : nn;
-    // B1: LQ, A <- A H_0 H_1 ... (reflectors on rows, stored in H)
-    for (int k = 0; k < r; ++k) {
-      if (wave == 0) {
-        wave_householder(v.A + (long)k * nn + k, nn - k, true, v.H + (long)k * nn + k, &sbeta, &szero);
-      }
-      __syncthreads();
-      if (!szero) {
-        for (int a = k + 1 + wave; a < m; a += nwaves) {
-          double2* row = v.A + (long)a * nn;
-          const double2* u = v.H + (long)k * nn;
-          double wr = 0.0, wi = 0.0;
-          for (int j = k + lane; j < nn; j += 64) {
-            const double2 p = cmul(row[j], u[j]);
-            wr += p.x;
-            wi += p.y;
-          }
-          const double2 w = cmk(wave_sum(wr), wave_sum(wi));
-          for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
-        }
-      }
-      // row k itself
-      for (int j = k + tid; j < nn; j += blockDim.x) v.A[(long)k * nn + j] = j == k ? sbeta : cmk(0.0, 0.0);
-      __syncthreads();
-    }
-    long long tc2 = clock64();
-    // B2: QR of the m x r lower-trapezoidal L (reflectors on columns)
-    for (int k = 0; k < r; ++k) {
-      const int L = m - k;
-      for (int i = tid; i < L; i += blockDim.x) uq[i] = v.A[(long)(k + i) * nn + k];
-      __syncthreads();
-      if (wave == 0) wave_householder(uq, L, false, uq, &sbeta, &szero);
-      __syncthreads();
-      if (!szero) {
-        for (int c = k + 1 + wave; c < r; c += nwaves) {
-          double wr = 0.0, wi = 0.0;
-          for (int i = lane; i < L; i += 64) {
-            const double2 p = cmul(cconj(uq[i]), v.A[(long)(k + i) * nn + c]);
-            wr += p.x;
-            wi += p.y;
-          }
-          const double2 w = cmk(wave_sum(wr), wave_sum(wi));
-          for (int i = lane; i < L; i += 64) {
-            double2* e = &v.A[(long)(k + i) * nn + c];
-            *e = csub(*e, cmul(uq[i], w));
-          }
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < L; i += blockDim.x) v.A[(long)(k + i) * nn + k] = i == 0 ? sbeta : cmk(0.0, 0.0);
-      __syncthreads();
-    }
-    long long tc3 = clock64();
-    // B3: one-sided Jacobi on the rows of the r x r upper triangle
-    int sweeps = 0;
-    bool converged = r < 2;
-    if (r >= 2) {
-      const int Pe = r + (r & 1);
-      for (int sw = 0; sw < sp.max_sweeps; ++sw) {
-        if (tid == 0) srot = 0;
-        __syncthreads();
-        for (int t = 0; t < Pe - 1; ++t) {
-          for (int kp = wave; kp < Pe / 2; kp += nwaves) {
-            const int p = rr_row(kp, t, Pe), q = rr_row(Pe - 1 - kp, t, Pe);
-            if (p >= r || q >= r) continue;
-            double2* rp = v.A + (long)p * nn;
-            double2* rq = v.A + (long)q * nn;
-            double2 xp[kMaxPerLane], xq[kMaxPerLane];
-            double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-            for (int e = 0; e < kMaxPerLane; ++e) {
-              const int j = lane + 64 * e;
-              if (j < r) {
-                xp[e] = rp[j];
-                xq[e] = rq[j];
-              } else {
-                xp[e] = cmk(0.0, 0.0);
-                xq[e] = cmk(0.0, 0.0);
-              }
-              al += cabs2(xp[e]);
-              be += cabs2(xq[e]);
-              // gamma = sum p_j conj(q_j)
-              gr += xp[e].x * xq[e].x + xp[e].y * xq[e].y;
-              gi += xp[e].y * xq[e].x - xp[e].x * xq[e].y;
-            }
-            al = wave_sum(al);
-            be = wave_sum(be);
-            gr = wave_sum(gr);
-            gi = wave_sum(gi);
-            const double ag = sqrt(gr * gr + gi * gi);
-            if (!(al > 0.0 && be > 0.0) || !(ag > sp.tol * sqrt(al) * sqrt(be))) continue;
-            const double zeta = (be - al) / (2.0 * ag);
-            double tt;
-            if (fabs(zeta) > 1e150)
-              tt = 0.5 / zeta;
-            else
-              tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-            const double2 e_ip = cmk(gr / ag, gi / ag);  // gamma / |gamma|
-            const double2 s_ip = cscale(e_ip, sn);       // s e^{i phi}
-            const double2 s_im = cconj(s_ip);             // s e^{-i phi}
-#pragma unroll
-            for (int e = 0; e < kMaxPerLane; ++e) {
-              const int j = lane + 64 * e;
-              if (j < r) {
-                const double2 np = csub(cscale(xp[e], cs), cmul(s_ip, xq[e]));
-                const double2 nq = cadd(cmul(s_im, xp[e]), cscale(xq[e], cs));
-                rp[j] = np;
-                rq[j] = nq;
-              }
-            }
-            if (lane == 0) srot = 1;
-          }
-          __syncthreads();
-        }
-        sweeps = sw + 1;
-        const int any = srot;
-        __syncthreads();
-        if (!any) {
-          converged = true;
-          break;
-        }
-      }
-    }
-    long long tc4 = clock64();
-    // B4: back-transform rows: [F, 0] H_{r-1} ... H_0 -> s_k w_k^H
-    for (int a = wave; a < r; a += nwaves) {
-      double2* row = v.A + (long)a * nn;
-      for (int j = r + lane; j < nn; j += 64) row[j] = cmk(0.0, 0.0);
-      for (int k = r - 1; k >= 0; --k) {
-        const double2* u = v.H + (long)k * nn;
-        double wr = 0.0, wi = 0.0;
-        for (int j = k + lane; j < nn; j += 64) {
-          const double2 p = cmul(row[j], u[j]);
-          wr += p.x;
-          wi += p.y;
-        }
-        const double2 w = cmk(wave_sum(wr), wave_sum(wi));
-        for (int j = k + lane; j < nn; j += 64) row[j] = csub(row[j], cmul(w, cconj(u[j])));
-      }
-      double s2 = 0.0;
-      for (int j = lane; j < nn; j += 64) s2 += cabs2(row[j]);
-      s2 = wave_sum(s2);
-      if (lane == 0) v.S[a] = sqrt(s2);
-    }
-    __syncthreads();
-
-    long long tc5 = clock64();
-    // ---- Phase C: truncate (Eq. 9), update (Eq. 10) --------------------------
-    for (int a = tid; a < r; a += blockDim.x) {
-      const double sa = v.S[a];
-      int rank = 0;
-      for (int q = 0; q < r; ++q) {
-        const double sq = v.S[q];
-        rank += (sq > sa || (sq == sa && q < a)) ? 1 : 0;
-      }
-      v.P[rank] = a;
-    }
-    __syncthreads();
-    __shared__ int schi;
-    __shared__ double snorm;
     if (tid == 0) {
-      const double s1 = v.S[v.P[0]];
-      if (!(s1 > 0.0) || !isfinite(s1)) {
-        *v.flags |= kFlagNumeric;
-        sabort = 1;
-      } else {
-        int nz = 0;
-        for (int q = 0; q < r; ++q) nz += v.S[q] > sp.cutoff_rel * s1 ? 1 : 0;
-        const int keep = nz < b.max_bond ? nz : b.max_bond;
-        double kept = 0.0, disc = 0.0;
-        for (int q = 0; q < r; ++q) {
-          const double s = v.S[v.P[q]];
-          if (q < keep)
-            kept += s * s;
-          else
-            disc += s * s;
-        }
-        const double d = disc / (kept + disc);
-        schi = keep;
-        snorm = sqrt(kept);
-        v.stats[kStatDisc] += d;
-        if (d > v.stats[kStatMaxDisc]) v.stats[kStatMaxDisc] = d;
-        if (keep > v.stats[kStatMaxChi]) v.stats[kStatMaxChi] = keep;
-        if (sweeps > v.stats[kStatSweeps]) v.stats[kStatSweeps] = sweeps;
-        v.stats[kStatSweepSum] += sweeps;
-        {
-          const double cl = chil, cmd = chim, cr = chir;
-          const double mm = m > nn ? m : nn, nm = m > nn ? nn : m;
-          v.stats[kStatFlops] += 32.0 * cl * cmd * cr + 128.0 * cl * cr + 4.0 * (4.0 * mm * nm * nm + 8.0 * nm * nm * nm) +
-                                 8.0 * double(m) * double(nn) * keep;
-        }
-        if (!converged) *v.flags |= kFlagNoConv;
-      }
+      double kept = 0.0;
+      for (int k = 0; k < keep; ++k) kept += L.sig[k] * L.sig[k];
+      const double d = L.sdisc / (kept + L.sdisc);
+      L.snorm = sqrt(kept);
+      v.stats[kStatDisc] += d;
+      if (d > v.stats[kStatMaxDisc]) v.stats[kStatMaxDisc] = d;
+      if (keep > v.stats[kStatMaxChi]) v.stats[kStatMaxChi] = keep;
+      if (sweeps > v.stats[kStatSweeps]) v.stats[kStatSweeps] = sweeps;
+      v.stats[kStatSweepSum] += sweeps;
+      if (fell_back) v.stats[kStatFallbacks] += 1.0;
+      if (used_bisect && !fell_back) v.stats[kStatBisect] += 1.0;
+      if (!conv) *v.flags |= kFlagNoConv;
+      const double cl = chil, cmd = chim, cr = chir;
+      const double mm = m > nn ? m : nn, nm = qmin;
+      v.stats[kStatFlops] += 32.0 * cl * cmd * cr + 128.0 * cl * cr + 4.0 * (4.0 * mm * nm * nm + 8.0 * nm * nm * nm) +
+                             8.0 * double(m) * double(nn) * keep;
     }
     __syncthreads();
-    if (sabort) return;
-    const int keep = schi;
-    const double nrm = snorm;
-    // sorted, normalised rows -> W (keep x nn) and site n+1 (Eq. 10: B_{n+1} = V)
+    const double nrm = L.snorm;
+    // B_{n+1} = kept rows of W^H (Eq. 10); lambda_n = S_kept / ||S_kept||
     for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
       const int k = idx / nn, col = idx - k * nn;
-      const int src = v.P[k];
-      const double2 w = cscale(v.A[(long)src * nn + col], 1.0 / v.S[src]);
-      v.W[idx] = w;
       const int jj = col / chir, c = col - jj * chir;
-      Bn1[(long)(2 * k + jj) * capr_r + c] = w;
+      Bn1[(long)(2 * k + jj) * capr_r + c] = v.W[idx];
     }
-    for (int k = tid; k < keep; k += blockDim.x) v.lam[b.lam_off[n] + k] = v.S[v.P[k]] / nrm;
+    for (int k = tid; k < keep; k += blockDim.x) v.lam[b.lam_off[n] + k] = L.sig[k] / nrm;
     __syncthreads();
-    // B_n = M W^H / ||S_kept||  (Eq. 10, no division by Schmidt values)
-    bgemm<false, true>(m, keep, nn, v.M, nn, v.W, nn, Bn, capl_r, cmk(1.0 / nrm, 0.0), false, lds_gemm);
+    // B_n = M W / ||S_kept||  (Eq. 10: no division by Schmidt values)
+    bgemm<false, true>(m, keep, nn, v.M, nn, v.W, nn, Bn, capl_r, cmk(1.0 / nrm, 0.0), false, L.gemm);
     if (tid == 0) {
       v.chi[n + 1] = keep;
-      const long long tc6 = clock64();
-      v.stats[kStatCycContract] += double(tc1 - tc0);
-      v.stats[kStatCycLQ] += double(tc2 - tc1);
-      v.stats[kStatCycQR] += double(tc3 - tc2);
-      v.stats[kStatCycJacobi] += double(tc4 - tc3);
-      v.stats[kStatCycBack] += double(tc5 - tc4);
-      v.stats[kStatCycUpdate] += double(tc6 - tc5);
+      const long long te = clock64();
+      v.stats[kStatCycContract] += double(tc[1] - tc[0]);
+      v.stats[kStatCycLQ] += double(tc[2] - tc[1]);
+      v.stats[kStatCycQR] += double(tc[3] - tc[2]);
+      v.stats[kStatCycJacobi] += double(tc[4] - tc[3]);
+      v.stats[kStatCycBack] += double(tc[5] - tc[4]);
+      v.stats[kStatCycUpdate] += double(te - tc[5]);
     }
     __syncthreads();
   }

@@ -43,6 +43,7 @@ class q2c_opts(C.Structure):
         ("svd_tol", C.c_double),
         ("slots", C.c_int),
         ("hbm_budget_bytes", C.c_size_t),
+        ("svd_algorithm", C.c_int),
     ]
 
 
@@ -64,9 +65,11 @@ class q2c_stats(C.Structure):
         ("gate_launches", C.c_int),
         ("n_circuits", C.c_int),
         ("cycles", C.c_double * 6),
+        ("svd_bisect_gates", C.c_double),
+        ("svd_fallbacks", C.c_double),
     ]
 
-    PHASES = ("contract", "lq", "qr", "jacobi", "back", "update")
+    PHASES = ("contract", "reduce", "values", "vectors", "back", "update")
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "cycles"}
