@@ -216,7 +216,7 @@ __device__ __forceinline__ int rr_row(int pos, int t, int P) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + t) % (P - 1));
 }
 
-constexpr int kMaxPerLane = 8;  // Jacobi row length <= 512
+
 constexpr int kQB = 128;        // bisection path: q = min(m, n) <= kQB
 constexpr int kKB = 64;         // bisection path: kept vectors <= kKB
 
@@ -224,7 +224,12 @@ constexpr int kKB = 64;         // bisection path: kept vectors <= kKB
 struct GateLds {
   double2 gemm[2 * 64 * 8];
   double2 O[16];
-  double2 uq[512], wq[512], vq[512], zq[512];
+  union {
+    struct {
+      double2 uq[512], wq[512], vq[512], zq[512];  // reflector work vectors
+    };
+    double Y[kQB * kKB];  // real kept vectors of the bidiagonal (bisection path)
+  };
   double2 dc[kQB], ec[kQB], pa[kQB], pb[kQB];  // bidiagonal and its phases
   double t[2 * kQB], t2[2 * kQB];               // Golub-Kahan tridiagonal
   double sig[512];                              // kept singular values, descending
@@ -242,17 +247,54 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal with zero
-// diagonal and squared off-diagonals t2[b0 .. b1-2] (indices b0 .. b1-1):
-// LDL^T Sturm count with tiny pivots replaced by -pivmin.
-__device__ int tgk_count(const double* t2, int b0, int b1, double x, double pivmin) {
-  double q = -x;
-  int c = q < 0.0 ? 1 : 0;
-  for (int i = b0; i < b1 - 1; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = -x - t2[i] / q;
-    c += q < 0.0 ? 1 : 0;
+// diagonal and squared off-diagonals t2[b0 .. b1-2] (indices b0 .. b1-1).
+// With p_{-1} = 1, p_0 = -x, p_i = -x p_{i-1} - t2[i-1] p_{i-2}, the count is
+// the number of sign changes of the sequence (a zero takes the sign opposite
+// to its predecessor); a zero off-diagonal restarts the recurrence with the
+// current sign.  Division-free; kept in range by power-of-two rescaling.
+__device__ int tgk_count1(const double* t2, int b0, int b1, double x) {
+  double pp = 1.0, p = -x;
+  double sg = p < 0.0 ? -1.0 : 1.0;
+  int c = p <= 0.0 ? 1 : 0;
+  if (p == 0.0) sg = -1.0;
+  // entries are scaled to |t| <= 1 and |x| <= 1: four steps grow the values
+  // by at most 2^4 and shrink them by at most t^8, so range checks every
+  // fourth step suffice
+  int i = b0;
+  while (i < b1 - 1) {
+    const int lim = i + 4 < b1 - 1 ? i + 4 : b1 - 1;
+    for (; i < lim; ++i) {
+      const double tt = t2[i];
+      double pn;
+      if (tt == 0.0) {
+        pp = sg;
+        pn = -x * sg;
+      } else {
+        pn = fma(-x, p, -tt * pp);
+        pp = p;
+      }
+      p = pn;
+      const double sn = pn > 0.0 ? 1.0 : (pn < 0.0 ? -1.0 : -sg);
+      c += sn != sg ? 1 : 0;
+      sg = sn;
+    }
+    const double mg = fmax(fabs(p), fabs(pp));
+    if (mg > 1e100 || (mg < 1e-100 && mg > 0.0)) {
+      const int e = ilogb(mg);
+      p = ldexp(p, -e);
+      pp = ldexp(pp, -e);
+    }
   }
   return c;
+}
+
+// 1/d to full double precision: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
 // ---- Phase A: Theta = B_n B_{n+1}, gate mixing (Eq. 7), lambda scaling (Eq. 8)
@@ -437,6 +479,12 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
       }
     }
     gersh = fmax(gersh, L.t[nt - 1]);
+    // scale to |t| <= 1 (eigenvalues scale by 1/gersh, vectors unchanged)
+    const double sc = gersh > 0.0 ? 1.0 / gersh : 1.0;
+    for (int i = 0; i < nt; ++i) {
+      L.t[i] *= sc;
+      L.t2[i] = L.t[i] * L.t[i];
+    }
     L.blo[nb] = start;
     L.bhi[nb] = 2 * q;
     ++nb;
@@ -446,42 +494,45 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
   }
   __syncthreads();
   const int nT = 2 * q;
-  const double pivmin = 2.3e-308 * fmax(1.0, L.stmax * L.stmax);
+  const double pivmin = 2.3e-308;  // T is scaled to norm <= 1
+  const double tscale = L.sgersh;   // singular values = scaled values * tscale
   const int kk = D < q ? D : q;
-  // -- bisection: 4 lanes per value, 5-section, 24 steps (interval / 5^24)
-  if (tid < 4 * kKB) {
-    const int j0 = tid >> 2, s4 = tid & 3;
+  // -- bisection on the scaled T: 8 lanes (one point each) per value ->
+  // 9-section, 18 steps (9^18 > 1e17)
+  {
+    const int j0 = tid >> 3, s8 = tid & 7;
     const int j = j0 < kk ? j0 : kk - 1;
     const int idx = nT - 1 - j;  // the value has exactly idx eigenvalues below it
-    double lo = 0.0, hi = L.sgersh * (1.0 + 1e-14) + 1e-300;
-    const int base = lane & ~3;
-    for (int it = 0; it < 24; ++it) {
-      const double w = (hi - lo) * 0.2;
-      const double x = lo + (s4 + 1) * w;
-      const int c = tgk_count(L.t2, 0, nT, x, pivmin);
-      double nlo = lo, nhi = hi;
+    double lo = 0.0, hi = 1.0 + 1e-14;
+    for (int it = 0; it < 18; ++it) {
+      const double w = (hi - lo) * (1.0 / 9.0);
+      const double x = lo + (s8 + 1) * w;
+      const int c = tgk_count1(L.t2, 0, nT, x);
+      double nlo = c <= idx ? x : lo;
+      double nhi = c <= idx ? hi : x;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int cs = __shfl(c, base + s, 64);
-        const double xs = lo + (s + 1) * w;
-        if (cs <= idx) nlo = fmax(nlo, xs);
-        else nhi = fmin(nhi, xs);
+      for (int o = 1; o < 8; o <<= 1) {
+        nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+        nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
       }
       lo = nlo;
       hi = nhi;
     }
-    if (s4 == 0 && j0 < kk) L.sig[j0] = 0.5 * (lo + hi);
+    if (s8 == 0 && j0 < kk) L.sig[j0] = 0.5 * (lo + hi);  // scaled
   }
   __syncthreads();
   if (tid == 0) {
     int keep = -1;
     const double s0 = L.sig[0];
-    if (s0 > 0.0 && isfinite(s0)) {
-      const int nz = nT - tgk_count(L.t2, 0, nT, cutoff * s0, pivmin);
+    if (s0 > 0.0 && isfinite(s0) && tscale > 0.0) {
+      const int nz = nT - tgk_count1(L.t2, 0, nT, cutoff * s0);
       keep = nz < kk ? nz : kk;
       if (keep < 1) keep = 1;
       double kept = 0.0;
-      for (int j = 0; j < keep; ++j) kept += L.sig[j] * L.sig[j];
+      for (int j = 0; j < keep; ++j) {
+        const double sj = L.sig[j] * tscale;
+        kept += sj * sj;
+      }
       L.sdisc = fmax(0.0, L.stot - kept);
     }
     L.skeep = keep;
@@ -492,23 +543,23 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
   const int keep = L.skeep;
   if (keep < 0) return -1;
   // -- vectors: one lane per kept value, spread over 4 waves
-  // scratch layout (5 q kk <= 5 ws^2 doubles of the 8 ws^2 available)
+  // global scratch: 4 q kk <= 4 ws^2 doubles of the 8 ws^2 available
   const int KV = kk;
   double* Dp = v.V;                    // [2q][KV]: D+ pivots, then the vector
   double* Dm = v.V + (long)nT * KV;    // [2q][KV]: D- pivots
-  double* Y = v.V + 2L * nT * KV;      // [q][KV]: real vectors
+  double* Y = L.Y;                     // [q][kKB]: real vectors (LDS)
   if (tid < 4 * kKB) {
     const int j = (tid & 63) * 4 + (tid >> 6);
     if (j < keep) {
-      const double sj = L.sig[j];
+      const double sj = L.sig[j];  // scaled
       const double tol = 1e-13 * L.sig[0];
       int inst = 0;
       for (int jp = 0; jp < j; ++jp) inst += fabs(L.sig[jp] - sj) <= tol ? 1 : 0;
       int b0 = L.blo[0], b1 = L.bhi[0], seen = 0;
       bool found = false;
       for (int bk = 0; bk < L.snblk && !found; ++bk) {
-        const int mult = tgk_count(L.t2, L.blo[bk], L.bhi[bk], sj + tol, pivmin) -
-                         tgk_count(L.t2, L.blo[bk], L.bhi[bk], sj - tol, pivmin);
+        const int mult = tgk_count1(L.t2, L.blo[bk], L.bhi[bk], sj + tol) -
+                         tgk_count1(L.t2, L.blo[bk], L.bhi[bk], sj - tol);
         if (mult > 0 && seen + mult > inst) {
           b0 = L.blo[bk];
           b1 = L.bhi[bk];
@@ -516,43 +567,39 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
         }
         seen += mult;
       }
-      double nrm2 = 0.0;
-      for (int i = 0; i < nT; ++i) Dp[i * KV + j] = 0.0;
+      double nrm2 = 1.0;
       if (b1 - b0 == 1) {
         Dp[b0 * KV + j] = 1.0;
-        nrm2 = 1.0;
       } else {
-        // forward D+ and backward D- pivots of (T - s I) on the block
+        // forward pivots D+ of (T - s I) on the block
         double dd = -sj;
         Dp[b0 * KV + j] = dd;
         for (int i = b0 + 1; i < b1; ++i) {
           if (fabs(dd) < pivmin) dd = -pivmin;
-          dd = -sj - L.t2[i - 1] / dd;
+          dd = fma(-L.t2[i - 1], rcp_nr(dd), -sj);
           Dp[i * KV + j] = dd;
         }
+        // backward pivots D- and the twist index r = argmin |D+ + D- + s|
         dd = -sj;
         Dm[(b1 - 1) * KV + j] = dd;
+        int r = b1 - 1;
+        double gmin = fabs(Dp[(b1 - 1) * KV + j]);
         for (int i = b1 - 2; i >= b0; --i) {
           if (fabs(dd) < pivmin) dd = -pivmin;
-          dd = -sj - L.t2[i] / dd;
+          dd = fma(-L.t2[i], rcp_nr(dd), -sj);
           Dm[i * KV + j] = dd;
-        }
-        int r = b0;
-        double gmin = 1e308;
-        for (int i = b0; i < b1; ++i) {
-          const double g = fabs(Dp[i * KV + j] + Dm[i * KV + j] + sj);
-          if (g < gmin) {
+          const double g = fabs(Dp[i * KV + j] + dd + sj);
+          if (g <= gmin) {
             gmin = g;
             r = i;
           }
         }
         // twisted solve: z_r = 1, up with L+, down with U-
         double z = 1.0;
-        nrm2 = 1.0;
         for (int i = r - 1; i >= b0; --i) {
           double dpi = Dp[i * KV + j];
           if (fabs(dpi) < pivmin) dpi = -pivmin;
-          z = -(L.t[i] / dpi) * z;
+          z = -(L.t[i] * rcp_nr(dpi)) * z;
           Dp[i * KV + j] = z;
           nrm2 += z * z;
         }
@@ -561,103 +608,135 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
         for (int i = r + 1; i < b1; ++i) {
           double dmi = Dm[i * KV + j];
           if (fabs(dmi) < pivmin) dmi = -pivmin;
-          z = -(L.t[i - 1] / dmi) * z;
+          z = -(L.t[i - 1] * rcp_nr(dmi)) * z;
           Dp[i * KV + j] = z;
           nrm2 += z * z;
         }
       }
       const double inv = 1.0 / sqrt(nrm2);
       const int off = trans ? 1 : 0;  // X = A: right vectors (even); X = A^H: left vectors (odd)
-      for (int k = 0; k < q; ++k) Y[k * KV + j] = Dp[(2 * k + off) * KV + j] * inv;
+      for (int k = 0; k < q; ++k) {
+        const int i = 2 * k + off;
+        Y[k * kKB + j] = (i >= b0 && i < b1) ? Dp[i * KV + j] * inv : 0.0;
+      }
     }
   }
   __syncthreads();
-  // -- CholQR2 on Y (q x keep)
+  for (int j = tid; j < keep; j += blockDim.x) L.sig[j] *= tscale;  // unscaled singular values
+  __syncthreads();
+  // -- CholQR2 on Y (q x keep), all in LDS
   for (int pass = 0; pass < 2; ++pass) {
-    for (int idx = tid; idx < keep * keep; idx += blockDim.x) {
-      const int a = idx / keep, c = idx - a * keep;
-      if (c > a) continue;
-      double s = 0.0;
-      for (int k = 0; k < q; ++k) s += Y[k * KV + a] * Y[k * KV + c];
-      L.G[a * kKB + c] = s;
+    // Gram, 4x4 register tiles of the lower triangle
+    const int nb4 = (keep + 3) >> 2;
+    for (int tIdx = tid; tIdx < nb4 * nb4; tIdx += blockDim.x) {
+      const int ba = tIdx / nb4, bc = tIdx - ba * nb4;
+      if (bc > ba) continue;
+      double acc[4][4] = {};
+      for (int k = 0; k < q; ++k) {
+        double ya[4], yc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ya[u] = Y[k * kKB + 4 * ba + u];
+          yc[u] = Y[k * kKB + 4 * bc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], yc[w], acc[u][w]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int a = 4 * ba + u, c = 4 * bc + w;
+          if (a < keep && c <= a) L.G[a * kKB + c] = acc[u][w];
+        }
     }
     __syncthreads();
-    if (wave == 0) {
-      bool ok = true;
-      for (int j = 0; j < keep; ++j) {
-        const double djj = L.G[j * kKB + j];
-        if (!(djj > 1e-10) || !isfinite(djj)) ok = false;
-        const double ljj = sqrt(fmax(djj, 1e-300));
-        wave_sync();
-        for (int a = j + 1 + lane; a < keep; a += 64) L.G[a * kKB + j] /= ljj;
-        if (lane == 0) L.G[j * kKB + j] = ljj;
-        wave_sync();
-        for (int a = j + 1 + lane; a < keep; a += 64) {
-          const double laj = L.G[a * kKB + j];
-          for (int c = j + 1; c <= a; ++c) L.G[a * kKB + c] -= laj * L.G[c * kKB + j];
-        }
-        wave_sync();
+    // right-looking Cholesky, lower triangle in place
+    for (int j = 0; j < keep; ++j) {
+      const double djj = L.G[j * kKB + j];
+      if (!(djj > 1e-10) || !isfinite(djj)) {
+        if (tid == 0) L.sfail = 1;
+        break;
       }
-      if (lane == 0) L.sfail = ok ? 0 : 1;
+      const double ljj = sqrt(djj);
+      __syncthreads();
+      for (int a = j + 1 + tid; a < keep; a += blockDim.x) L.G[a * kKB + j] /= ljj;
+      if (tid == 0) L.G[j * kKB + j] = ljj;
+      __syncthreads();
+      const int rem = keep - j - 1;
+      for (int e = tid; e < rem * rem; e += blockDim.x) {
+        const int a = j + 1 + e / rem, c = j + 1 + e % rem;
+        if (c <= a) L.G[a * kKB + c] -= L.G[a * kKB + j] * L.G[c * kKB + j];
+      }
+      __syncthreads();
     }
     __syncthreads();
     if (L.sfail) return -1;
-    // Y <- Y L^{-T}, row by row
+    // Y <- Y L^{-T}: forward substitution per row of Y, 4 rows per wave-quarter
     for (int k = tid; k < q; k += blockDim.x) {
       for (int c = 0; c < keep; ++c) {
-        double s = Y[k * KV + c];
-        for (int e = 0; e < c; ++e) s -= Y[k * KV + e] * L.G[c * kKB + e];
-        Y[k * KV + c] = s / L.G[c * kKB + c];
+        double sacc = Y[k * kKB + c];
+        for (int e = 0; e < c; ++e) sacc -= Y[k * kKB + e] * L.G[c * kKB + e];
+        Y[k * kKB + c] = sacc / L.G[c * kKB + c];
       }
     }
     __syncthreads();
   }
   tcyc[2] = clock64();
-  // -- complex vectors of the bidiagonal, then through the reflectors
+  // -- complex vectors of the bidiagonal, then through the reflectors.
+  // Wt rows j (length nn) in global; per reflector: dots for all kept
+  // vectors (4 lanes x 128 vectors per pass), one barrier, then the update.
   double2* Wt = v.W;  // [keep][nn]
   for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
     const int j = idx / nn, k = idx - j * nn;
     double2 w = cmk(0.0, 0.0);
-    if (k < q) w = cscale(trans ? L.pa[k] : L.pb[k], Y[k * KV + j]);
+    if (k < q) w = cscale(trans ? L.pa[k] : L.pb[k], Y[k * kKB + j]);
     Wt[idx] = w;
   }
   __syncthreads();
-  for (int j = wave; j < keep; j += nwaves) {
-    double2* w = Wt + (long)j * nn;
-    if (!trans) {
-      for (int k = q - 2; k >= 0; --k) {
-        const double2* u = X + (long)k * ldx + k + 1;
-        const int len = q - k - 1;
-        double dr = 0.0, di = 0.0;
-        for (int i = lane; i < len; i += 64) {
-          const double2 pr = cmul(cconj(u[i]), w[k + 1 + i]);
+  const int kstart = trans ? q - 1 : q - 2;
+  for (int k = kstart; k >= 0; --k) {
+    const int off = trans ? k : k + 1;
+    const int len = trans ? p - k : q - k - 1;
+    // u_i = X[k+i][k] (left reflector, trans) or X[k][k+1+i] (right reflector)
+    for (int i = tid; i < len; i += blockDim.x) L.uq[i] = trans ? X[(long)(k + i) * ldx + k] : X[(long)k * ldx + k + 1 + i];
+    __syncthreads();
+    {
+      const int j = tid >> 3, s8 = tid & 7;  // 8 lanes per vector, 64 vectors
+      double dr = 0.0, di = 0.0;
+      if (j < keep) {
+        const double2* w = Wt + (long)j * nn + off;
+        for (int i = s8; i < len; i += 8) {
+          const double2 pr = cmul(cconj(L.uq[i]), w[i]);
           dr += pr.x;
           di += pr.y;
         }
-        const double2 dot = cmk(wave_sum(dr), wave_sum(di));
-        for (int i = lane; i < len; i += 64) w[k + 1 + i] = csub(w[k + 1 + i], cmul(u[i], dot));
       }
-    } else {
-      for (int k = q - 1; k >= 0; --k) {
-        const int len = p - k;
-        double dr = 0.0, di = 0.0;
-        for (int i = lane; i < len; i += 64) {
-          const double2 pr = cmul(cconj(X[(long)(k + i) * ldx + k]), w[k + i]);
-          dr += pr.x;
-          di += pr.y;
-        }
-        const double2 dot = cmk(wave_sum(dr), wave_sum(di));
-        for (int i = lane; i < len; i += 64) w[k + i] = csub(w[k + i], cmul(X[(long)(k + i) * ldx + k], dot));
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        dr += __shfl_xor(dr, o, 64);
+        di += __shfl_xor(di, o, 64);
       }
+      if (s8 == 0 && j < keep) L.wq[j] = cmk(dr, di);
     }
-    for (int i = lane; i < nn; i += 64) w[i] = cconj(w[i]);  // rows of W^H
+    __syncthreads();
+    for (int idx = tid; idx < keep * len; idx += blockDim.x) {
+      const int j = idx / len, i = idx - j * len;
+      double2* e = Wt + (long)j * nn + off + i;
+      *e = csub(*e, cmul(L.uq[i], L.wq[j]));
+    }
+    __syncthreads();
   }
+  for (int idx = tid; idx < keep * nn; idx += blockDim.x) Wt[idx] = cconj(Wt[idx]);  // rows of W^H
   __syncthreads();
   return keep;
 }
 
 // ---- Phase B (fallback): LQ + QR preconditioning and one-sided row Jacobi.
 // Same outputs as svd_bisect.  *sweeps_out / *conv_out report convergence.
+template <int kMaxPerLane>  // Jacobi row length <= 64 * kMaxPerLane
 __device__ int svd_jacobi(const DevBatch& b, SlotView& v, GateLds& L, int m, int nn, SvdParams sp, int* sweeps_out,
                           bool* conv_out, long long* tcyc) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
@@ -849,6 +928,9 @@ __device__ int svd_jacobi(const DevBatch& b, SlotView& v, GateLds& L, int m, int
   return keep;
 }
 
+// kSmall: every bond <= 64 (two-site matrices <= 128 x 128): bisection SVD
+// with a compact Jacobi fallback.  Otherwise: Jacobi with rows up to 512.
+template <bool kSmall>
 __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restrict__ gsite,
                                                   const int* __restrict__ grot, const double2* __restrict__ gpre,
                                                   const double2* __restrict__ gpost, const double* __restrict__ phi_all,
@@ -893,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     int keep = -1, sweeps = 0;
     bool conv = true, used_bisect = false, fell_back = false;
     long long tb[3] = {tc[1], tc[1], tc[1]};
-    if (sp.algo == 0 && qmin <= kQB && b.max_bond <= kKB) {
+    if (kSmall && sp.algo == 0 && qmin <= kQB) {
       used_bisect = true;
       keep = svd_bisect(v, L, m, nn, b.max_bond, sp.cutoff_rel, tb);
       if (keep < 0) {
@@ -901,7 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
         restore_mprime(b, v, n, chil, chir);
       }
     }
-    if (keep < 0) keep = svd_jacobi(b, v, L, m, nn, sp, &sweeps, &conv, tb);
+    if (keep < 0) keep = svd_jacobi<kSmall ? 2 : 8>(b, v, L, m, nn, sp, &sweeps, &conv, tb);
     tc[2] = tb[0];
     tc[3] = tb[1];
     tc[4] = tb[2];
@@ -1117,8 +1199,14 @@ hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d
 hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, const double2* d_pre,
                         const double2* d_post, int g0, int g1, int n_rot, SvdParams sp, hipStream_t st) {
   if (g1 <= g0) return hipSuccess;
-  hipLaunchKernelGGL(k_gates, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot,
-                     g0, g1, sp);
+  int cm = 1;
+  for (int i = 0; i <= b.n_qubits; ++i) cm = cm > b.cap[i] ? cm : b.cap[i];
+  if (cm <= kKB)
+    hipLaunchKernelGGL(k_gates<true>, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi,
+                       n_rot, g0, g1, sp);
+  else
+    hipLaunchKernelGGL(k_gates<false>, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi,
+                       n_rot, g0, g1, sp);
   return hipGetLastError();
 }
 

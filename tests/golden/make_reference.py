@@ -30,6 +30,19 @@ CASES = {
 }
 
 
+def statevector_energy(name):
+    n_orb, n_elec, si, st, D, _, _ = CASES[name]
+    I = random_integrals(n_orb, n_elec, si)
+    th = random_theta(n_uccsd_params(n_orb, n_elec), st)
+    n = 2 * n_orb
+    c_id, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri))
+    rots = uccsd.rotations(n, n_elec)
+    phis = uccsd.rotation_angles(rots, th)
+    pa = sv.PauliApplier(n)
+    psi = sv.evolve(n, uccsd.hf_occupation(n, n_elec), rots, phis, pa)
+    return sv.energy(pa, c_id, terms, psi)
+
+
 def run(name):
     n_orb, n_elec, si, st, D, do_sv, second = CASES[name]
     I = random_integrals(n_orb, n_elec, si)
@@ -62,12 +75,17 @@ def run(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(CASES)
+    args = sys.argv[1:]
+    sv_only = "--statevector-only" in args
+    names = [a for a in args if not a.startswith("--")] or list(CASES)
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     data["_source"] = "written by tests/golden/make_reference.py from oracle/ only"
     for nm in names:
         print("running", nm, flush=True)
-        data[nm] = run(nm)
+        if sv_only:
+            data.setdefault(nm, {})["energy_statevector"] = statevector_energy(nm)
+        else:
+            data[nm] = run(nm)
         print(json.dumps(data[nm]), flush=True)
         with open(OUT, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
