@@ -217,28 +217,35 @@ __device__ __forceinline__ int rr_row(int pos, int t, int P) {
 }
 
 
-constexpr int kQB = 128;        // bisection path: q = min(m, n) <= kQB
-constexpr int kKB = 64;         // bisection path: kept vectors <= kKB
+constexpr int kQB = 128;      // bisection path: q = min(m, n) <= kQB
+constexpr int kKB = 64;       // bisection path: kept vectors <= kKB
+constexpr int kZS = kKB + 1;  // row stride (doubles) of the vector work array
 
-// Static LDS of the gate kernel (about 100 KB of the 160 KB per CU).
+// Static LDS of the gate kernel (about 150 KB of the 160 KB per CU).
 struct GateLds {
-  double2 gemm[2 * 64 * 8];
   double2 O[16];
-  union {
-    struct {
-      double2 uq[512], wq[512], vq[512], zq[512];  // reflector work vectors
-    };
-    double Y[kQB * kKB];  // real kept vectors of the bidiagonal (bisection path)
-  };
   double2 dc[kQB], ec[kQB], pa[kQB], pb[kQB];  // bidiagonal and its phases
-  double t[2 * kQB], t2[2 * kQB];               // Golub-Kahan tridiagonal
-  double sig[512];                              // kept singular values, descending
-  double G[kKB * kKB];                          // Gram / Cholesky factor
-  int blo[2 * kQB], bhi[2 * kQB];               // blocks of the split tridiagonal
+  double t[2 * kQB], t2[2 * kQB + 8];          // Golub-Kahan tridiagonal (t2 zero-padded)
+  double sig[512];                             // kept singular values, descending
+  double ldiag[kKB];                           // reciprocal Cholesky diagonal
+  int blo[2 * kQB], bhi[2 * kQB];              // blocks of the split tridiagonal
   double red[16];
   double2 sbeta;
+  unsigned long long serr;
   int szero, srot, sabort, skeep, sfail, snblk;
   double sdisc, stot, snorm, sgersh, stmax;
+  union {
+    double2 gemm[2 * 64 * 8];  // block-GEMM tiles
+    struct {
+      double2 uq[512], wq[512], vq[512], zq[512];  // Jacobi-path work vectors
+    };
+    struct {
+      double2 col[kQB], row[kQB], w[kQB];
+      double2 part[8][kQB];
+      double nrm[8], rnrm;
+    } bd;                      // exchange area of the bidiagonalisation
+    double Z[2 * kQB * kZS];   // twisted factorisations, kept vectors, Gram; later reflectors
+  };
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -246,44 +253,91 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Number of eigenvalues below x of the symmetric tridiagonal with zero
-// diagonal and squared off-diagonals t2[b0 .. b1-2] (indices b0 .. b1-1).
-// With p_{-1} = 1, p_0 = -x, p_i = -x p_{i-1} - t2[i-1] p_{i-2}, the count is
-// the number of sign changes of the sequence (a zero takes the sign opposite
-// to its predecessor); a zero off-diagonal restarts the recurrence with the
-// current sign.  Division-free; kept in range by power-of-two rescaling.
-__device__ int tgk_count1(const double* t2, int b0, int b1, double x) {
-  double pp = 1.0, p = -x;
-  double sg = p < 0.0 ? -1.0 : 1.0;
-  int c = p <= 0.0 ? 1 : 0;
-  if (p == 0.0) sg = -1.0;
-  // entries are scaled to |t| <= 1 and |x| <= 1: four steps grow the values
-  // by at most 2^4 and shrink them by at most t^8, so range checks every
-  // fourth step suffice
-  int i = b0;
-  while (i < b1 - 1) {
-    const int lim = i + 4 < b1 - 1 ? i + 4 : b1 - 1;
-    for (; i < lim; ++i) {
-      const double tt = t2[i];
-      double pn;
-      if (tt == 0.0) {
-        pp = sg;
-        pn = -x * sg;
-      } else {
-        pn = fma(-x, p, -tt * pp);
-        pp = p;
-      }
-      p = pn;
-      const double sn = pn > 0.0 ? 1.0 : (pn < 0.0 ? -1.0 : -sg);
-      c += sn != sg ? 1 : 0;
-      sg = sn;
+// ---- cross-lane sums without the LDS pipe (DPP row ops and gfx950 lane swaps).
+// Every lane of the wave must execute them.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Sum over the 16 lanes of a row; every lane of the row gets the same value.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_mov<0x128>(v);  // row_ror:8
+  v += dpp_mov<0x124>(v);  // row_ror:4
+  v += dpp_mov<0x4E>(v);   // quad_perm 2,3,0,1
+  v += dpp_mov<0xB1>(v);   // quad_perm 1,0,3,2
+  return v;
+}
+// Sum over the four lanes of a quad.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0xB1>(v);
+  return v;
+}
+// Lanes below 32 return a(l) + a(l + 32); the others b(l - 32) + b(l).
+__device__ __forceinline__ double pair_sum32(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// Lanes in even 16-lane rows return a(l) + a(l + 16); odd rows b(l - 16) + b(l).
+__device__ __forceinline__ double pair_sum16(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double2 pair_sum32(double2 a, double2 b) {
+  return cmk(pair_sum32(a.x, b.x), pair_sum32(a.y, b.y));
+}
+__device__ __forceinline__ double2 pair_sum16(double2 a, double2 b) {
+  return cmk(pair_sum16(a.x, b.x), pair_sum16(a.y, b.y));
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal with zero diagonal
+// whose squared off-diagonals are t2[0 .. n-2]: the sign changes along the
+// leading minors p_0 = 1, p_1 = -x, p_{i+1} = -x p_i - t2[i-1] p_{i-1}.  A zero
+// off-diagonal needs no special case (minors of a block-diagonal matrix
+// factorise).  With |t| <= 1 and 0 < x <= 1 the values grow by less than 2^6
+// over eight steps, so a power-of-two renormalisation every eight steps keeps
+// them in range.  Division-free.
+__device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
+  const double nx = -x;
+  double pm = 1.0, pc = nx;
+  unsigned sp = (unsigned)__double2hiint(pc) >> 31;
+  int c = (int)sp;
+  int i = 1;
+  for (; i + 8 <= n; i += 8) {
+    double tt[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tt[u] = t2[i - 1 + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double pn = fma(nx, pc, -tt[u] * pm);
+      const unsigned s = (unsigned)__double2hiint(pn) >> 31;
+      c += (int)(s ^ sp);
+      sp = s;
+      pm = pc;
+      pc = pn;
     }
-    const double mg = fmax(fabs(p), fabs(pp));
-    if (mg > 1e100 || (mg < 1e-100 && mg > 0.0)) {
-      const int e = ilogb(mg);
-      p = ldexp(p, -e);
-      pp = ldexp(pp, -e);
+    const int e = max(__builtin_amdgcn_frexp_exp(pc), __builtin_amdgcn_frexp_exp(pm));
+    if (e > 400 || e < -400) {
+      pc = ldexp(pc, -e);
+      pm = ldexp(pm, -e);
     }
+  }
+  for (; i < n; ++i) {
+    const double pn = fma(nx, pc, -t2[i - 1] * pm);
+    const unsigned s = (unsigned)__double2hiint(pn) >> 31;
+    c += (int)(s ^ sp);
+    sp = s;
+    pm = pc;
+    pc = pn;
   }
   return c;
 }
@@ -335,7 +389,7 @@ __device__ void gate_contract(const DevBatch& b, SlotView& v, GateLds& L, int n,
   __syncthreads();
 }
 
-// M' = lambda * M again (the bisection path overwrites A).
+// M' = lambda * M again (before the Jacobi fallback).
 __device__ void restore_mprime(const DevBatch& b, SlotView& v, int n, int chil, int chir) {
   const int nn = 2 * chir;
   for (int idx = threadIdx.x; idx < 2 * chil * nn; idx += blockDim.x) {
@@ -346,156 +400,292 @@ __device__ void restore_mprime(const DevBatch& b, SlotView& v, int n, int chil, 
   __syncthreads();
 }
 
-// ---- Phase B (default): SVD by Golub-Kahan bidiagonalisation, bisection on
-// the Golub-Kahan tridiagonal for the kept singular values, twisted
-// factorisations for their vectors, CholQR2 and back-transformation.
-// Output: L.sig[0..keep) descending, v.W rows = kept rows of W^H (n wide),
-// L.sdisc.  Returns keep, or -1 if the vectors could not be certified (the
-// caller then uses the Jacobi path).  Requires min(m, n) <= kQB, D <= kKB.
-__device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double cutoff, long long* tcyc) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+// ---- Phase B (default), step 1: Golub-Kahan bidiagonalisation of the p x q
+// matrix X (p >= q <= 128) held in registers.  Thread (r0, c0), r0 = 4 wave +
+// lane / 16, c0 = lane % 16, owns X[r0 + 32 rs][c0 + 16 cs] for rs < 4, cs < 8,
+// so that a wave holds whole rows and the rows and columns still active at
+// step k are spread evenly over all waves.  Step k (in phase KS = k / 16,
+// which fixes the register slot of column k and of row k at compile time)
+// applies H_k from the left to zero column k below the diagonal and G_k from
+// the right to zero row k right of the superdiagonal.  The reflectors needed
+// for the back-transformation go to global memory: G_k (stored conjugated, as
+// applied to columns) when X = M', H_k when X = M'^H.
+struct BdArgs {
+  double2* Hg;
+  int ldh, p, q, r0, c0, lane, wave;
+  bool trans;
+};
+
+template <int KS>
+__device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const BdArgs& a, GateLds& L) {
+  constexpr int RSK = KS / 2, CSK = KS;
+  const int tid = threadIdx.x;
+  // ---- H_k on column k, rows k .. p-1
+  {
+    const bool own = a.c0 == (k & 15);
+    double s = 0.0;
+#pragma unroll
+    for (int rs = RSK; rs < 4; ++rs) {
+      const int i = a.r0 + 32 * rs;
+      const double2 xv = i >= k ? X[rs][CSK] : cmk(0.0, 0.0);
+      if (own) L.bd.col[i] = xv;
+      s += cabs2(xv);
+    }
+    s = own ? s : 0.0;
+    s = pair_sum16(s, s);
+    s = pair_sum32(s, s);
+    if (own && a.lane < 16) L.bd.nrm[a.wave] = s;
+  }
+  __syncthreads();
+  double2 u[4];
+  bool zero;
+  {
+    double n2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) n2 += L.bd.nrm[w];
+    const double nx = sqrt(n2);
+    zero = !(nx > 0.0);
+    const double2 x0 = L.bd.col[k];
+    const double ax = sqrt(cabs2(x0));
+    const double2 ph = ax > 0.0 ? cscale(x0, 1.0 / ax) : cmk(1.0, 0.0);
+    const double inv = zero ? 0.0 : 1.0 / sqrt(nx * (nx + ax));
+    if (tid == 0) L.dc[k] = zero ? cmk(0.0, 0.0) : cscale(ph, -nx);
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs) {
+      const int i = a.r0 + 32 * rs;
+      double2 uv = cmk(0.0, 0.0);
+      if (rs >= RSK && i >= k && !zero) uv = i == k ? cscale(ph, (ax + nx) * inv) : cscale(L.bd.col[i], inv);
+      u[rs] = uv;
+      if (a.trans && a.c0 == 0 && rs >= RSK && i >= k && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
+    }
+  }
+  if (!zero) {
+    // partial w_j = sum_i conj(u_i) X_ij over this thread's rows
+    double2 wp[8];
+#pragma unroll
+    for (int cs = 0; cs < 8; ++cs) {
+      double2 acc = cmk(0.0, 0.0);
+      if (cs >= CSK) {
+#pragma unroll
+        for (int rs = RSK; rs < 4; ++rs) {
+          const double2 uc = u[rs], x = X[rs][cs];
+          acc.x = fma(uc.x, x.x, acc.x);
+          acc.x = fma(uc.y, x.y, acc.x);
+          acc.y = fma(uc.x, x.y, acc.y);
+          acc.y = fma(-uc.y, x.x, acc.y);
+        }
+      }
+      wp[cs] = acc;
+    }
+    // reduce-scatter over the four lanes sharing c0: lane bits (5, 4) = (b5, b4)
+    // keep column slots 4 b5 + 2 b4 + {0, 1}
+    double2 h[4], g[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[i] = pair_sum32(wp[i], wp[4 + i]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) g[i] = pair_sum16(h[i], h[2 + i]);
+    const int sb = 4 * ((a.lane >> 5) & 1) + 2 * ((a.lane >> 4) & 1);
+    L.bd.part[a.wave][a.c0 + 16 * sb] = g[0];
+    L.bd.part[a.wave][a.c0 + 16 * (sb + 1)] = g[1];
+  }
+  __syncthreads();
+  if (!zero && tid < kQB) {
+    double2 s = cmk(0.0, 0.0);
+    if (tid > k) {
+#pragma unroll
+      for (int w = 0; w < 8; ++w) s = cadd(s, L.bd.part[w][tid]);
+    }
+    L.bd.w[tid] = s;
+  }
+  __syncthreads();
+  if (!zero) {
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) {
+      const double2 wj = L.bd.w[a.c0 + 16 * cs];
+#pragma unroll
+      for (int rs = RSK; rs < 4; ++rs) X[rs][cs] = csub(X[rs][cs], cmul(u[rs], wj));
+    }
+  }
+  if (k >= a.q - 1) return;
+  // ---- G_k on row k, columns k+1 .. q-1
+  {
+    const bool own = a.r0 == (k & 31);
+    double s = 0.0;
+    if (own) {
+#pragma unroll
+      for (int cs = CSK; cs < 8; ++cs) {
+        const int j = a.c0 + 16 * cs;
+        const double2 xv = j > k ? X[RSK][cs] : cmk(0.0, 0.0);
+        L.bd.row[j] = xv;
+        s += cabs2(xv);
+      }
+    }
+    s = row16_sum(s);
+    if (own && a.c0 == 0) L.bd.rnrm = s;
+  }
+  __syncthreads();
+  const double nx = sqrt(L.bd.rnrm);
+  const bool rzero = !(nx > 0.0);
+  const double2 x0 = L.bd.row[k + 1];
+  const double ax = sqrt(cabs2(x0));
+  const double2 ph = ax > 0.0 ? cscale(x0, 1.0 / ax) : cmk(1.0, 0.0);
+  const double inv = rzero ? 0.0 : 1.0 / sqrt(nx * (nx + ax));
+  if (tid == 0) L.ec[k] = rzero ? cmk(0.0, 0.0) : cscale(ph, -nx);
+  double2 vv[8];
+#pragma unroll
+  for (int cs = 0; cs < 8; ++cs) {
+    const int j = a.c0 + 16 * cs;
+    double2 x = cmk(0.0, 0.0);
+    if (cs >= CSK && j > k && !rzero) x = cconj(j == k + 1 ? cscale(ph, (ax + nx) * inv) : cscale(L.bd.row[j], inv));
+    vv[cs] = x;
+    if (!a.trans && a.r0 == 0 && cs >= CSK && j > k && j < a.q) a.Hg[(long)k * a.ldh + j] = x;
+  }
+  if (rzero) return;
+  // z_i = sum_j X_ij v_j; rows are whole within a 16-lane row of the wave
+  double2 zp[4];
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs) {
+    double2 acc = cmk(0.0, 0.0);
+    if (rs >= RSK) {
+#pragma unroll
+      for (int cs = CSK; cs < 8; ++cs) cfma(acc, X[rs][cs], vv[cs]);
+      acc.x = row16_sum(acc.x);
+      acc.y = row16_sum(acc.y);
+      if (a.r0 + 32 * rs <= k) acc = cmk(0.0, 0.0);
+    }
+    zp[rs] = acc;
+  }
+#pragma unroll
+  for (int rs = RSK; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) X[rs][cs] = csub(X[rs][cs], cmul(zp[rs], cconj(vv[cs])));
+}
+
+template <int KS>
+__device__ __forceinline__ void bd_phase(double2 (&X)[4][8], const BdArgs& a, GateLds& L) {
+  if (16 * KS >= a.q) return;
+  for (int k1 = 0; k1 < 16; ++k1) {
+    const int k = 16 * KS + k1;
+    if (k >= a.q) break;
+    bd_step<KS>(X, k, a, L);
+  }
+}
+
+// ---- Phase B (default): SVD by Golub-Kahan bidiagonalisation (registers),
+// bisection on the Golub-Kahan tridiagonal for the kept singular values,
+// twisted factorisations for their vectors (LDS), CholQR and back-
+// transformation through the reflectors.  Output: L.sig[0..keep) descending,
+// v.W rows = kept rows of W^H (n wide), L.sdisc.  Returns keep, or -1 if the
+// vectors could not be certified (the caller then uses the Jacobi path).
+// Requires min(m, n) <= kQB, max(m, n) <= ws, D <= kKB.
+__device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double cutoff, int ws, long long* tcyc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool trans = m < nn;
   const int p = trans ? nn : m, q = trans ? m : nn;
-  double2* X = trans ? v.H : v.A;
-  const int ldx = q;
-  if (trans) {
-    // X = A^H, p = nn rows, q = m columns
-    for (int idx = tid; idx < p * q; idx += blockDim.x) {
-      const int i = idx / q, j = idx - i * q;
-      X[idx] = cconj(v.A[(long)j * nn + i]);
-    }
-    __syncthreads();
+  double2* Hg = v.H;  // reflector k in row k (stride ws)
+  {
+    BdArgs a;
+    a.Hg = Hg;
+    a.ldh = ws;
+    a.p = p;
+    a.q = q;
+    a.r0 = 4 * wave + (lane >> 4);
+    a.c0 = lane & 15;
+    a.lane = lane;
+    a.wave = wave;
+    a.trans = trans;
+    double2 X[4][8];
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+      for (int cs = 0; cs < 8; ++cs) {
+        const int i = a.r0 + 32 * rs, j = a.c0 + 16 * cs;
+        double2 x = cmk(0.0, 0.0);
+        if (i < p && j < q) x = trans ? cconj(v.A[(long)j * nn + i]) : v.A[(long)i * nn + j];
+        X[rs][cs] = x;
+      }
+    bd_phase<0>(X, a, L);
+    bd_phase<1>(X, a, L);
+    bd_phase<2>(X, a, L);
+    bd_phase<3>(X, a, L);
+    bd_phase<4>(X, a, L);
+    bd_phase<5>(X, a, L);
+    bd_phase<6>(X, a, L);
+    bd_phase<7>(X, a, L);
   }
-  // -- Golub-Kahan: H_k from the left on column k, G_k from the right on row k
-  for (int k = 0; k < q; ++k) {
-    const int Lc = p - k;
-    for (int i = tid; i < Lc; i += blockDim.x) L.uq[i] = X[(long)(k + i) * ldx + k];
-    __syncthreads();
-    if (wave == 0) {
-      bool z;
-      wave_householder(L.uq, Lc, false, L.uq, &L.sbeta, &z);
-      if (lane == 0) L.szero = z;
-    }
-    __syncthreads();
-    if (tid == 0) L.dc[k] = L.sbeta;
-    const int nw = q - k - 1;
-    if (!L.szero && nw > 0) {
-      // w_j = sum_i conj(u_i) X[k+i][k+1+j]: 4 row groups x up to 128 columns per pass
-      for (int j0 = 0; j0 < nw; j0 += 128) {
-        const int jj = j0 + (tid & 127), g = tid >> 7;
-        double wr = 0.0, wi = 0.0;
-        if (jj < nw) {
-          for (int i = g; i < Lc; i += 4) {
-            const double2 pr = cmul(cconj(L.uq[i]), X[(long)(k + i) * ldx + k + 1 + jj]);
-            wr += pr.x;
-            wi += pr.y;
-          }
-        }
-        L.zq[tid] = cmk(wr, wi);
-        __syncthreads();
-        if (tid < 128 && j0 + tid < nw)
-          L.wq[j0 + tid] = cadd(cadd(L.zq[tid], L.zq[tid + 128]), cadd(L.zq[tid + 256], L.zq[tid + 384]));
-        __syncthreads();
-      }
-      for (int idx = tid; idx < Lc * nw; idx += blockDim.x) {
-        const int i = idx / nw, jj = idx - i * nw;
-        double2* e = &X[(long)(k + i) * ldx + k + 1 + jj];
-        *e = csub(*e, cmul(L.uq[i], L.wq[jj]));
-      }
-    }
-    for (int i = tid; i < Lc; i += blockDim.x) X[(long)(k + i) * ldx + k] = L.uq[i];  // left reflector
-    __syncthreads();
-    if (nw > 0) {
-      if (wave == 0) {
-        bool z;
-        wave_householder(X + (long)k * ldx + k + 1, nw, true, L.vq, &L.sbeta, &z);
-        if (lane == 0) L.szero = z;
-      }
-      __syncthreads();
-      if (tid == 0) L.ec[k] = L.sbeta;
-      const int nr = p - k - 1;
-      if (!L.szero && nr > 0) {
-        // z_i = sum_j X[k+1+i][k+1+j] v_j, 4 lanes per row
-        for (int i0 = 0; i0 < nr; i0 += 128) {
-          const int ii = i0 + (tid >> 2), s4 = tid & 3;
-          double zr = 0.0, zi = 0.0;
-          if (ii < nr) {
-            for (int j = s4; j < nw; j += 4) {
-              const double2 pr = cmul(X[(long)(k + 1 + ii) * ldx + k + 1 + j], L.vq[j]);
-              zr += pr.x;
-              zi += pr.y;
-            }
-          }
-          zr += __shfl_xor(zr, 1, 64);
-          zi += __shfl_xor(zi, 1, 64);
-          zr += __shfl_xor(zr, 2, 64);
-          zi += __shfl_xor(zi, 2, 64);
-          if (s4 == 0 && ii < nr) L.zq[ii] = cmk(zr, zi);
-        }
-        __syncthreads();
-        for (int idx = tid; idx < nr * nw; idx += blockDim.x) {
-          const int i = idx / nw, j = idx - i * nw;
-          double2* e = &X[(long)(k + 1 + i) * ldx + k + 1 + j];
-          *e = csub(*e, cmul(L.zq[i], cconj(L.vq[j])));
-        }
-      }
-      for (int j = tid; j < nw; j += blockDim.x) X[(long)k * ldx + k + 1 + j] = L.vq[j];  // right reflector
-      __syncthreads();
-    }
-  }
+  __syncthreads();
   tcyc[0] = clock64();
   // -- real bidiagonal by diagonal phase scaling; Golub-Kahan tridiagonal t
-  if (tid == 0) {
-    double2 bk = cmk(1.0, 0.0);
-    double tmax = 0.0;
-    for (int k = 0; k < q; ++k) {
-      const double2 d = L.dc[k];
-      const double ad = sqrt(cabs2(d));
-      const double2 ak = ad > 0.0 ? cscale(cmul(d, bk), 1.0 / ad) : bk;
-      L.pa[k] = ak;
-      L.pb[k] = bk;
-      L.t[2 * k] = ad;
-      tmax = fmax(tmax, ad);
-      if (k + 1 < q) {
-        const double2 e = L.ec[k];
-        const double ae = sqrt(cabs2(e));
-        bk = ae > 0.0 ? cscale(cmul(ak, cconj(e)), 1.0 / ae) : cmk(1.0, 0.0);
-        L.t[2 * k + 1] = ae;
-        tmax = fmax(tmax, ae);
-      }
+  if (tid < q) {
+    const double2 d = L.dc[tid];
+    const double ad = sqrt(cabs2(d));
+    L.t[2 * tid] = ad;
+    L.pa[tid] = ad > 0.0 ? cscale(d, 1.0 / ad) : cmk(1.0, 0.0);
+    if (tid + 1 < q) {
+      const double2 e = L.ec[tid];
+      const double ae = sqrt(cabs2(e));
+      L.t[2 * tid + 1] = ae;
+      L.pb[tid + 1] = ae > 0.0 ? cscale(cconj(e), 1.0 / ae) : cmk(0.0, 0.0);
     }
-    const int nt = 2 * q - 1;
-    double gersh = 0.0;
-    int nb = 0, start = 0;
-    for (int i = 0; i < nt; ++i) {
-      if (L.t[i] <= 1e-15 * tmax) L.t[i] = 0.0;  // split at negligible entries
-      L.t2[i] = L.t[i] * L.t[i];
-      gersh = fmax(gersh, L.t[i] + (i > 0 ? L.t[i - 1] : 0.0));
-      if (L.t[i] == 0.0) {
-        L.blo[nb] = start;
-        L.bhi[nb] = i + 1;
-        ++nb;
-        start = i + 1;
-      }
-    }
-    gersh = fmax(gersh, L.t[nt - 1]);
-    // scale to |t| <= 1 (eigenvalues scale by 1/gersh, vectors unchanged)
-    const double sc = gersh > 0.0 ? 1.0 / gersh : 1.0;
-    for (int i = 0; i < nt; ++i) {
-      L.t[i] *= sc;
-      L.t2[i] = L.t[i] * L.t[i];
-    }
-    L.blo[nb] = start;
-    L.bhi[nb] = 2 * q;
-    ++nb;
-    L.snblk = nb;
-    L.sgersh = gersh;
-    L.stmax = tmax;
   }
   __syncthreads();
   const int nT = 2 * q;
-  const double pivmin = 2.3e-308;  // T is scaled to norm <= 1
-  const double tscale = L.sgersh;   // singular values = scaled values * tscale
+  if (wave == 0) {
+    if (lane == 0) {
+      // phases: a_k = (d_k/|d_k|) b_k, b_{k+1} = a_k conj(e_k)/|e_k| (b restarts at 1 after e_k = 0)
+      double2 bk = cmk(1.0, 0.0);
+#pragma unroll 4
+      for (int k = 0; k < q; ++k) {
+        const double2 ak = cmul(L.pa[k], bk);
+        const double2 ue = k + 1 < q ? L.pb[k + 1] : cmk(0.0, 0.0);
+        L.pa[k] = ak;
+        L.pb[k] = bk;
+        bk = (ue.x != 0.0 || ue.y != 0.0) ? cmul(ak, ue) : cmk(1.0, 0.0);
+      }
+    }
+    // split at negligible entries, scale to norm <= 1, find the blocks
+    double tm = 0.0;
+    for (int i = lane; i < nT - 1; i += 64) tm = fmax(tm, L.t[i]);
+    tm = wave_max(tm);
+    for (int i = lane; i < nT - 1; i += 64)
+      if (L.t[i] <= 1e-15 * tm) L.t[i] = 0.0;
+    wave_sync();
+    double gs = 0.0;
+    for (int i = lane; i < nT; i += 64) gs = fmax(gs, (i < nT - 1 ? L.t[i] : 0.0) + (i > 0 ? L.t[i - 1] : 0.0));
+    gs = wave_max(gs);
+    const double sc = gs > 0.0 ? 1.0 / gs : 1.0;
+    wave_sync();
+    for (int i = lane; i < nT + 7; i += 64) {
+      const double x = i < nT - 1 ? L.t[i] * sc : 0.0;
+      if (i < nT - 1) L.t[i] = x;
+      L.t2[i] = x * x;
+    }
+    wave_sync();
+    int nb = 0, start = 0;
+    for (int base = 0; base < nT - 1; base += 64) {
+      const int i = base + lane;
+      unsigned long long msk = __ballot(i < nT - 1 && L.t[i] == 0.0);
+      while (msk) {
+        const int ii = base + __ffsll((long long)msk) - 1;
+        msk &= msk - 1;
+        if (lane == 0) {
+          L.blo[nb] = start;
+          L.bhi[nb] = ii + 1;
+        }
+        ++nb;
+        start = ii + 1;
+      }
+    }
+    if (lane == 0) {
+      L.blo[nb] = start;
+      L.bhi[nb] = nT;
+      L.snblk = nb + 1;
+      L.sgersh = gs;
+      L.stmax = tm;
+    }
+  }
+  __syncthreads();
+  const double tscale = L.sgersh;  // singular values = scaled values * tscale
   const int kk = D < q ? D : q;
   // -- bisection on the scaled T: 8 lanes (one point each) per value ->
   // 9-section, 18 steps (9^18 > 1e17)
@@ -507,7 +697,7 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
     for (int it = 0; it < 18; ++it) {
       const double w = (hi - lo) * (1.0 / 9.0);
       const double x = lo + (s8 + 1) * w;
-      const int c = tgk_count1(L.t2, 0, nT, x);
+      const int c = sturm_count(L.t2, nT, x);
       double nlo = c <= idx ? x : lo;
       double nhi = c <= idx ? hi : x;
 #pragma unroll
@@ -525,7 +715,7 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
     int keep = -1;
     const double s0 = L.sig[0];
     if (s0 > 0.0 && isfinite(s0) && tscale > 0.0) {
-      const int nz = nT - tgk_count1(L.t2, 0, nT, cutoff * s0);
+      const int nz = nT - sturm_count(L.t2, nT, cutoff * s0);
       keep = nz < kk ? nz : kk;
       if (keep < 1) keep = 1;
       double kept = 0.0;
@@ -542,194 +732,268 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
   tcyc[1] = clock64();
   const int keep = L.skeep;
   if (keep < 0) return -1;
-  // -- vectors: one lane per kept value, spread over 4 waves
-  // global scratch: 4 q kk <= 4 ws^2 doubles of the 8 ws^2 available
-  const int KV = kk;
-  double* Dp = v.V;                    // [2q][KV]: D+ pivots, then the vector
-  double* Dm = v.V + (long)nT * KV;    // [2q][KV]: D- pivots
-  double* Y = L.Y;                     // [q][kKB]: real vectors (LDS)
-  if (tid < 4 * kKB) {
-    const int j = (tid & 63) * 4 + (tid >> 6);
-    if (j < keep) {
-      const double sj = L.sig[j];  // scaled
+  // -- vectors of T (one lane per kept value): twisted factorisation of T - s I
+  // inside the block that holds s.  Column j of Z: D+ pivots, then D- pivots,
+  // then the vector.  Rows 2k + off (k < q) of the vector are the bidiagonal's
+  // right vector (X = M') or left vector (X = M'^H).
+  const double pivmin = 2.3e-308;  // T is scaled to norm <= 1
+  const int off = trans ? 1 : 0;
+  double* Z = L.Z;
+  if (wave == 0 && lane < keep) {
+    const int j = lane;
+    const double sj = L.sig[j];  // scaled
+    int b0 = L.blo[0], b1 = L.bhi[0];
+    if (L.snblk > 1) {
+      // coincident values, which the split produces in pairs, go to distinct blocks
       const double tol = 1e-13 * L.sig[0];
       int inst = 0;
       for (int jp = 0; jp < j; ++jp) inst += fabs(L.sig[jp] - sj) <= tol ? 1 : 0;
-      int b0 = L.blo[0], b1 = L.bhi[0], seen = 0;
+      int seen = 0;
       bool found = false;
       for (int bk = 0; bk < L.snblk && !found; ++bk) {
-        const int mult = tgk_count1(L.t2, L.blo[bk], L.bhi[bk], sj + tol) -
-                         tgk_count1(L.t2, L.blo[bk], L.bhi[bk], sj - tol);
+        const int lo_ = L.blo[bk], n_ = L.bhi[bk] - lo_;
+        const int mult = sturm_count(L.t2 + lo_, n_, sj + tol) - sturm_count(L.t2 + lo_, n_, sj - tol);
         if (mult > 0 && seen + mult > inst) {
-          b0 = L.blo[bk];
-          b1 = L.bhi[bk];
+          b0 = lo_;
+          b1 = lo_ + n_;
           found = true;
         }
         seen += mult;
       }
-      double nrm2 = 1.0;
-      if (b1 - b0 == 1) {
-        Dp[b0 * KV + j] = 1.0;
-      } else {
-        // forward pivots D+ of (T - s I) on the block
-        double dd = -sj;
-        Dp[b0 * KV + j] = dd;
-        for (int i = b0 + 1; i < b1; ++i) {
-          if (fabs(dd) < pivmin) dd = -pivmin;
-          dd = fma(-L.t2[i - 1], rcp_nr(dd), -sj);
-          Dp[i * KV + j] = dd;
-        }
-        // backward pivots D- and the twist index r = argmin |D+ + D- + s|
-        dd = -sj;
-        Dm[(b1 - 1) * KV + j] = dd;
-        int r = b1 - 1;
-        double gmin = fabs(Dp[(b1 - 1) * KV + j]);
-        for (int i = b1 - 2; i >= b0; --i) {
-          if (fabs(dd) < pivmin) dd = -pivmin;
-          dd = fma(-L.t2[i], rcp_nr(dd), -sj);
-          Dm[i * KV + j] = dd;
-          const double g = fabs(Dp[i * KV + j] + dd + sj);
-          if (g <= gmin) {
-            gmin = g;
-            r = i;
-          }
-        }
-        // twisted solve: z_r = 1, up with L+, down with U-
-        double z = 1.0;
-        for (int i = r - 1; i >= b0; --i) {
-          double dpi = Dp[i * KV + j];
-          if (fabs(dpi) < pivmin) dpi = -pivmin;
-          z = -(L.t[i] * rcp_nr(dpi)) * z;
-          Dp[i * KV + j] = z;
-          nrm2 += z * z;
-        }
-        Dp[r * KV + j] = 1.0;
-        z = 1.0;
-        for (int i = r + 1; i < b1; ++i) {
-          double dmi = Dm[i * KV + j];
-          if (fabs(dmi) < pivmin) dmi = -pivmin;
-          z = -(L.t[i - 1] * rcp_nr(dmi)) * z;
-          Dp[i * KV + j] = z;
-          nrm2 += z * z;
-        }
+    }
+    double* zc = Z + j;  // element i at zc[i * kZS]
+    double nrm2 = 1.0;
+    if (b1 - b0 == 1) {
+      zc[b0 * kZS] = 1.0;
+    } else {
+      // forward pivots D+
+      double dd = -sj;
+      zc[b0 * kZS] = dd;
+      for (int i = b0 + 1; i < b1; ++i) {
+        if (fabs(dd) < pivmin) dd = -pivmin;
+        dd = fma(-L.t2[i - 1], rcp_nr(dd), -sj);
+        zc[i * kZS] = dd;
       }
-      const double inv = 1.0 / sqrt(nrm2);
-      const int off = trans ? 1 : 0;  // X = A: right vectors (even); X = A^H: left vectors (odd)
-      for (int k = 0; k < q; ++k) {
-        const int i = 2 * k + off;
-        Y[k * kKB + j] = (i >= b0 && i < b1) ? Dp[i * KV + j] * inv : 0.0;
+      // backward pivots D- (overwriting D+) and the twist r = argmin |D+ + D- + s|
+      dd = -sj;
+      int r = b1 - 1;
+      double gmin = fabs(zc[(b1 - 1) * kZS]);
+      zc[(b1 - 1) * kZS] = dd;
+      for (int i = b1 - 2; i >= b0; --i) {
+        if (fabs(dd) < pivmin) dd = -pivmin;
+        dd = fma(-L.t2[i], rcp_nr(dd), -sj);
+        const double g = fabs(zc[i * kZS] + dd + sj);
+        if (g <= gmin) {
+          gmin = g;
+          r = i;
+        }
+        zc[i * kZS] = dd;
       }
+      // forward pivots again above the twist
+      dd = -sj;
+      if (r > b0) zc[b0 * kZS] = dd;
+      for (int i = b0 + 1; i < r; ++i) {
+        if (fabs(dd) < pivmin) dd = -pivmin;
+        dd = fma(-L.t2[i - 1], rcp_nr(dd), -sj);
+        zc[i * kZS] = dd;
+      }
+      // twisted solve: z_r = 1, up with L+, down with U-
+      double z = 1.0;
+      for (int i = r - 1; i >= b0; --i) {
+        double dpi = zc[i * kZS];
+        if (fabs(dpi) < pivmin) dpi = -pivmin;
+        z = -(L.t[i] * rcp_nr(dpi)) * z;
+        zc[i * kZS] = z;
+        nrm2 += z * z;
+      }
+      zc[r * kZS] = 1.0;
+      z = 1.0;
+      for (int i = r + 1; i < b1; ++i) {
+        double dmi = zc[i * kZS];
+        if (fabs(dmi) < pivmin) dmi = -pivmin;
+        z = -(L.t[i - 1] * rcp_nr(dmi)) * z;
+        zc[i * kZS] = z;
+        nrm2 += z * z;
+      }
+    }
+    const double inv = 1.0 / sqrt(nrm2);
+    for (int k = 0; k < q; ++k) {
+      const int i = 2 * k + off;
+      zc[i * kZS] = (i >= b0 && i < b1) ? zc[i * kZS] * inv : 0.0;
     }
   }
   __syncthreads();
   for (int j = tid; j < keep; j += blockDim.x) L.sig[j] *= tscale;  // unscaled singular values
-  __syncthreads();
-  // -- CholQR2 on Y (q x keep), all in LDS
+  // -- CholQR on Y (q x keep): Y(k, j) = Yb[2 k kZS + j]; the Gram matrix
+  // lives in the interleaved rows no longer needed: G(a, c) = Gb[2 a kZS + c]
+  double* Yb = Z + off * kZS;
+  double* Gb = Z + (1 - off) * kZS;
   for (int pass = 0; pass < 2; ++pass) {
-    // Gram, 4x4 register tiles of the lower triangle
-    const int nb4 = (keep + 3) >> 2;
-    for (int tIdx = tid; tIdx < nb4 * nb4; tIdx += blockDim.x) {
-      const int ba = tIdx / nb4, bc = tIdx - ba * nb4;
-      if (bc > ba) continue;
+    if (tid == 0) L.serr = 0ull;
+    __syncthreads();
+    {
+      // lower triangle in 4 x 4 tiles; lanes l and l ^ 32 split the rows of Y
+      const int tile = (wave << 5) | (lane & 31), half = lane >> 5;
+      const int ta = tile >> 4, tc = tile & 15;
+      const bool act = 4 * ta < keep && tc <= ta;
       double acc[4][4] = {};
-      for (int k = 0; k < q; ++k) {
-        double ya[4], yc[4];
+      if (act) {
+        const int kh = (q + 1) >> 1;
+        const int k0 = half ? kh : 0, k1 = half ? q : kh;
+        for (int k = k0; k < k1; ++k) {
+          const double* yr = Yb + (long)(2 * k) * kZS;
+          double ya[4], yc[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ya[u] = Y[k * kKB + 4 * ba + u];
-          yc[u] = Y[k * kKB + 4 * bc + u];
+          for (int u = 0; u < 4; ++u) {
+            ya[u] = yr[4 * ta + u];
+            yc[u] = yr[4 * tc + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], yc[w], acc[u][w]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], yc[w], acc[u][w]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const int a = 4 * ba + u, c = 4 * bc + w;
-          if (a < keep && c <= a) L.G[a * kKB + c] = acc[u][w];
-        }
+        for (int w = 0; w < 4; ++w) acc[u][w] = pair_sum32(acc[u][w], acc[u][w]);
+      if (act && half == 0) {
+        double err = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int ra = 4 * ta + u, rc = 4 * tc + w;
+            if (ra < keep && rc <= ra) {
+              Gb[(long)(2 * ra) * kZS + rc] = acc[u][w];
+              err = fmax(err, fabs(acc[u][w] - (ra == rc ? 1.0 : 0.0)));
+            }
+          }
+        if (!(err <= 1e300)) err = 1e300;  // NaN or Inf
+        atomicMax(&L.serr, (unsigned long long)__double_as_longlong(err));
+      }
     }
     __syncthreads();
-    // right-looking Cholesky, lower triangle in place
-    for (int j = 0; j < keep; ++j) {
-      const double djj = L.G[j * kKB + j];
-      if (!(djj > 1e-10) || !isfinite(djj)) {
-        if (tid == 0) L.sfail = 1;
-        break;
-      }
-      const double ljj = sqrt(djj);
+    const double err = __longlong_as_double((long long)L.serr);
+    if (err >= 1e300) return -1;
+    if (err <= 1e-14) break;  // orthonormal to working precision
+    // right-looking Cholesky, lower triangle in place; reciprocal diagonal in ldiag
+    for (int jj = 0; jj < keep; ++jj) {
+      const double djj = Gb[(long)(2 * jj) * kZS + jj];
+      if (!(djj > 1e-10) || !isfinite(djj)) return -1;  // the same value in every thread
+      const double rinv = 1.0 / sqrt(djj);
+      for (int ra = jj + 1 + tid; ra < keep; ra += blockDim.x) Gb[(long)(2 * ra) * kZS + jj] *= rinv;
+      if (tid == 0) L.ldiag[jj] = rinv;
       __syncthreads();
-      for (int a = j + 1 + tid; a < keep; a += blockDim.x) L.G[a * kKB + j] /= ljj;
-      if (tid == 0) L.G[j * kKB + j] = ljj;
-      __syncthreads();
-      const int rem = keep - j - 1;
+      const int rem = keep - jj - 1;
       for (int e = tid; e < rem * rem; e += blockDim.x) {
-        const int a = j + 1 + e / rem, c = j + 1 + e % rem;
-        if (c <= a) L.G[a * kKB + c] -= L.G[a * kKB + j] * L.G[c * kKB + j];
+        const int ra = jj + 1 + e / rem, rc = jj + 1 + e % rem;
+        if (rc <= ra) Gb[(long)(2 * ra) * kZS + rc] -= Gb[(long)(2 * ra) * kZS + jj] * Gb[(long)(2 * rc) * kZS + jj];
       }
       __syncthreads();
     }
-    __syncthreads();
-    if (L.sfail) return -1;
-    // Y <- Y L^{-T}: forward substitution per row of Y, 4 rows per wave-quarter
-    for (int k = tid; k < q; k += blockDim.x) {
-      for (int c = 0; c < keep; ++c) {
-        double sacc = Y[k * kKB + c];
-        for (int e = 0; e < c; ++e) sacc -= Y[k * kKB + e] * L.G[c * kKB + e];
-        Y[k * kKB + c] = sacc / L.G[c * kKB + c];
-      }
-    }
-    __syncthreads();
-  }
-  tcyc[2] = clock64();
-  // -- complex vectors of the bidiagonal, then through the reflectors.
-  // Wt rows j (length nn) in global; per reflector: dots for all kept
-  // vectors (4 lanes x 128 vectors per pass), one barrier, then the update.
-  double2* Wt = v.W;  // [keep][nn]
-  for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
-    const int j = idx / nn, k = idx - j * nn;
-    double2 w = cmk(0.0, 0.0);
-    if (k < q) w = cscale(trans ? L.pa[k] : L.pb[k], Y[k * kKB + j]);
-    Wt[idx] = w;
-  }
-  __syncthreads();
-  const int kstart = trans ? q - 1 : q - 2;
-  for (int k = kstart; k >= 0; --k) {
-    const int off = trans ? k : k + 1;
-    const int len = trans ? p - k : q - k - 1;
-    // u_i = X[k+i][k] (left reflector, trans) or X[k][k+1+i] (right reflector)
-    for (int i = tid; i < len; i += blockDim.x) L.uq[i] = trans ? X[(long)(k + i) * ldx + k] : X[(long)k * ldx + k + 1 + i];
-    __syncthreads();
+    // Y <- Y L^{-T}: row k solves L x = y; thread (k, s4) holds entries s4 + 4 t
     {
-      const int j = tid >> 3, s8 = tid & 7;  // 8 lanes per vector, 64 vectors
-      double dr = 0.0, di = 0.0;
-      if (j < keep) {
-        const double2* w = Wt + (long)j * nn + off;
-        for (int i = s8; i < len; i += 8) {
-          const double2 pr = cmul(cconj(L.uq[i]), w[i]);
-          dr += pr.x;
-          di += pr.y;
+      const int k = tid >> 2, s4 = tid & 3;
+      double* yr = Yb + (long)(2 * k) * kZS;
+      double y[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int e = s4 + 4 * t;
+        y[t] = (k < q && e < keep) ? yr[e] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < kKB; ++c) {
+        if (c < keep) {
+          double part = 0.0;
+#pragma unroll
+          for (int t = 0; t < (c + 3) / 4; ++t) {
+            const int e = 4 * t + s4;
+            if (e < c) part = fma(y[t], Gb[(long)(2 * c) * kZS + e], part);
+          }
+          part = quad_sum(part);
+          if (s4 == (c & 3)) y[c >> 2] = (y[c >> 2] - part) * L.ldiag[c];
         }
       }
 #pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        dr += __shfl_xor(dr, o, 64);
-        di += __shfl_xor(di, o, 64);
+      for (int t = 0; t < 16; ++t) {
+        const int e = s4 + 4 * t;
+        if (k < q && e < keep) yr[e] = y[t];
       }
-      if (s8 == 0 && j < keep) L.wq[j] = cmk(dr, di);
     }
     __syncthreads();
-    for (int idx = tid; idx < keep * len; idx += blockDim.x) {
-      const int j = idx / len, i = idx - j * len;
-      double2* e = Wt + (long)j * nn + off + i;
-      *e = csub(*e, cmul(L.uq[i], L.wq[j]));
-    }
-    __syncthreads();
+    if (err <= 1e-4) break;  // one pass leaves orthogonality at working precision
   }
-  for (int idx = tid; idx < keep * nn; idx += blockDim.x) Wt[idx] = cconj(Wt[idx]);  // rows of W^H
+  tcyc[2] = clock64();
+  // -- complex vectors of the bidiagonal, then through the reflectors, held in
+  // registers: thread (vl, pl) = (lane / 16, lane % 16) of wave w holds vectors
+  // j = 8 w + 2 vl + s (s < 2) at positions pl + 16 e (e < 8)
+  {
+    const int vl = lane >> 4, pl = lane & 15;
+    const double2* phase = trans ? L.pa : L.pb;
+    double2 Wr[2][8];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 8 * wave + 2 * vl + s, pos = pl + 16 * e;
+        double2 x = cmk(0.0, 0.0);
+        if (j < keep && pos < q) x = cscale(phase[pos], Yb[(long)(2 * pos) * kZS + j]);
+        Wr[s][e] = x;
+      }
+    __syncthreads();
+    // stage the reflectors in LDS, packed: reflector k has len_k entries from st_k
+    double2* R = reinterpret_cast<double2*>(L.Z);
+    const int kstart = trans ? q - 1 : q - 2;
+    for (int k = wave; k <= kstart; k += 8) {
+      const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
+      const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
+      for (int i = lane; i < len; i += 64) R[ro + i] = Hg[(long)k * ws + st + i];
+    }
+    __syncthreads();
+    for (int k = kstart; k >= 0; --k) {
+      const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
+      const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
+      double2 u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int pos = pl + 16 * e;
+        u[e] = (pos >= st && pos < st + len) ? R[ro + pos - st] : cmk(0.0, 0.0);
+      }
+      double2 d[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        double2 acc = cmk(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (16 * e + 15 < st || 16 * e >= st + len) continue;  // the same for all lanes
+          const double2 uc = u[e], x = Wr[s][e];
+          acc.x = fma(uc.x, x.x, acc.x);
+          acc.x = fma(uc.y, x.y, acc.x);
+          acc.y = fma(uc.x, x.y, acc.y);
+          acc.y = fma(-uc.y, x.x, acc.y);
+        }
+        acc.x = row16_sum(acc.x);
+        acc.y = row16_sum(acc.y);
+        d[s] = acc;
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (16 * e + 15 < st || 16 * e >= st + len) continue;
+          Wr[s][e] = csub(Wr[s][e], cmul(u[e], d[s]));
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 8 * wave + 2 * vl + s, pos = pl + 16 * e;
+        if (j < keep && pos < nn) v.W[(long)j * nn + pos] = cconj(Wr[s][e]);  // rows of W^H
+      }
+  }
   __syncthreads();
   return keep;
 }
@@ -977,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     long long tb[3] = {tc[1], tc[1], tc[1]};
     if (kSmall && sp.algo == 0 && qmin <= kQB) {
       used_bisect = true;
-      keep = svd_bisect(v, L, m, nn, b.max_bond, sp.cutoff_rel, tb);
+      keep = svd_bisect(v, L, m, nn, b.max_bond, sp.cutoff_rel, b.ws, tb);
       if (keep < 0) {
         fell_back = true;
         restore_mprime(b, v, n, chil, chir);
