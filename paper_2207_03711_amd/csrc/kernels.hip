@@ -231,7 +231,6 @@ struct GateLds {
   int blo[2 * kQB], bhi[2 * kQB];              // blocks of the split tridiagonal
   double red[16];
   double2 sbeta;
-  unsigned long long serr;
   int szero, srot, sabort, skeep, sfail, snblk;
   double sdisc, stot, snorm, sgersh, stmax;
   union {
@@ -309,22 +308,24 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
   const double nx = -x;
   double pm = 1.0, pc = nx;
-  unsigned sp = (unsigned)__double2hiint(pc) >> 31;
-  int c = (int)sp;
+  unsigned last = (unsigned)__double2hiint(pc) >> 31;  // sign bit of p_1
+  int c = (int)last;                                   // p_0 = 1 > 0
   int i = 1;
   for (; i + 8 <= n; i += 8) {
     double tt[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) tt[u] = t2[i - 1 + u];
+    // shift register of sign bits: bit 8 holds the sign of p_i, bit 0 that of p_{i+8}
+    unsigned w = last;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double pn = fma(nx, pc, -tt[u] * pm);
-      const unsigned s = (unsigned)__double2hiint(pn) >> 31;
-      c += (int)(s ^ sp);
-      sp = s;
       pm = pc;
       pc = pn;
+      w = __builtin_amdgcn_alignbit(w, (unsigned)__double2hiint(pn), 31u);
     }
+    c += __builtin_popcount((w ^ (w >> 1)) & 0xFFu);
+    last = w & 1u;
     const int e = max(__builtin_amdgcn_frexp_exp(pc), __builtin_amdgcn_frexp_exp(pm));
     if (e > 400 || e < -400) {
       pc = ldexp(pc, -e);
@@ -333,9 +334,9 @@ __device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
   }
   for (; i < n; ++i) {
     const double pn = fma(nx, pc, -t2[i - 1] * pm);
-    const unsigned s = (unsigned)__double2hiint(pn) >> 31;
-    c += (int)(s ^ sp);
-    sp = s;
+    const unsigned sg = (unsigned)__double2hiint(pn) >> 31;
+    c += (int)(sg ^ last);
+    last = sg;
     pm = pc;
     pc = pn;
   }
@@ -349,6 +350,53 @@ __device__ __forceinline__ double rcp_nr(double d) {
   r = fma(r, e, r);
   e = fma(-d, r, 1.0);
   return fma(r, e, r);
+}
+
+// 1/sqrt(x) for normal x > 0: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * r, r, 0.5);
+  r = fma(r, e, r);
+  e = fma(-h * r, r, 0.5);
+  return fma(r, e, r);
+}
+
+// x -= a * b and x -= a * conj(b), four fused multiply-adds each
+__device__ __forceinline__ void cfms(double2& x, double2 a, double2 b) {
+  x.x = fma(-a.x, b.x, x.x);
+  x.x = fma(a.y, b.y, x.x);
+  x.y = fma(-a.x, b.y, x.y);
+  x.y = fma(-a.y, b.x, x.y);
+}
+__device__ __forceinline__ void cfms_conj(double2& x, double2 a, double2 b) {
+  x.x = fma(-a.x, b.x, x.x);
+  x.x = fma(-a.y, b.y, x.x);
+  x.y = fma(a.x, b.y, x.y);
+  x.y = fma(-a.y, b.x, x.y);
+}
+
+// Householder scalars for a vector with squared norm n2 and leading entry x0:
+// H = I - u u^H maps x to beta e_0 with beta = -ph |x|, ph = x0 / |x0| (1 if
+// x0 = 0); u = x * inv except u_0 = ph (|x0| + |x|) inv.  Norms below 1e-280
+// count as zero (no reflection).
+struct HhScalars {
+  double2 ph, beta;
+  double inv, head;  // u_0 = ph * head
+  bool zero;
+};
+__device__ __forceinline__ HhScalars hh_scalars(double n2, double2 x0) {
+  HhScalars h;
+  h.zero = !(n2 > 1e-280);
+  const double nx = h.zero ? 0.0 : n2 * rsq_nr(n2);
+  const double ax2 = cabs2(x0);
+  const double ra = ax2 > 1e-280 ? rsq_nr(ax2) : 0.0;
+  const double ax = ax2 * ra;
+  h.ph = ax2 > 1e-280 ? cscale(x0, ra) : cmk(1.0, 0.0);
+  h.inv = h.zero ? 0.0 : rsq_nr(nx * (nx + ax));
+  h.head = (ax + nx) * h.inv;
+  h.beta = h.zero ? cmk(0.0, 0.0) : cscale(h.ph, -nx);
+  return h;
 }
 
 // ---- Phase A: Theta = B_n B_{n+1}, gate mixing (Eq. 7), lambda scaling (Eq. 8)
@@ -443,18 +491,14 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
     double n2 = 0.0;
 #pragma unroll
     for (int w = 0; w < 8; ++w) n2 += L.bd.nrm[w];
-    const double nx = sqrt(n2);
-    zero = !(nx > 0.0);
-    const double2 x0 = L.bd.col[k];
-    const double ax = sqrt(cabs2(x0));
-    const double2 ph = ax > 0.0 ? cscale(x0, 1.0 / ax) : cmk(1.0, 0.0);
-    const double inv = zero ? 0.0 : 1.0 / sqrt(nx * (nx + ax));
-    if (tid == 0) L.dc[k] = zero ? cmk(0.0, 0.0) : cscale(ph, -nx);
+    const HhScalars h = hh_scalars(n2, L.bd.col[k]);
+    zero = h.zero;
+    if (tid == 0) L.dc[k] = h.beta;
 #pragma unroll
     for (int rs = 0; rs < 4; ++rs) {
       const int i = a.r0 + 32 * rs;
       double2 uv = cmk(0.0, 0.0);
-      if (rs >= RSK && i >= k && !zero) uv = i == k ? cscale(ph, (ax + nx) * inv) : cscale(L.bd.col[i], inv);
+      if (rs >= RSK && i >= k && !zero) uv = i == k ? cscale(h.ph, h.head) : cscale(L.bd.col[i], h.inv);
       u[rs] = uv;
       if (a.trans && a.c0 == 0 && rs >= RSK && i >= k && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
     }
@@ -503,7 +547,7 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
     for (int cs = CSK; cs < 8; ++cs) {
       const double2 wj = L.bd.w[a.c0 + 16 * cs];
 #pragma unroll
-      for (int rs = RSK; rs < 4; ++rs) X[rs][cs] = csub(X[rs][cs], cmul(u[rs], wj));
+      for (int rs = RSK; rs < 4; ++rs) cfms(X[rs][cs], u[rs], wj);
     }
   }
   if (k >= a.q - 1) return;
@@ -524,19 +568,15 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
     if (own && a.c0 == 0) L.bd.rnrm = s;
   }
   __syncthreads();
-  const double nx = sqrt(L.bd.rnrm);
-  const bool rzero = !(nx > 0.0);
-  const double2 x0 = L.bd.row[k + 1];
-  const double ax = sqrt(cabs2(x0));
-  const double2 ph = ax > 0.0 ? cscale(x0, 1.0 / ax) : cmk(1.0, 0.0);
-  const double inv = rzero ? 0.0 : 1.0 / sqrt(nx * (nx + ax));
-  if (tid == 0) L.ec[k] = rzero ? cmk(0.0, 0.0) : cscale(ph, -nx);
+  const HhScalars h = hh_scalars(L.bd.rnrm, L.bd.row[k + 1]);
+  const bool rzero = h.zero;
+  if (tid == 0) L.ec[k] = h.beta;
   double2 vv[8];
 #pragma unroll
   for (int cs = 0; cs < 8; ++cs) {
     const int j = a.c0 + 16 * cs;
     double2 x = cmk(0.0, 0.0);
-    if (cs >= CSK && j > k && !rzero) x = cconj(j == k + 1 ? cscale(ph, (ax + nx) * inv) : cscale(L.bd.row[j], inv));
+    if (cs >= CSK && j > k && !rzero) x = cconj(j == k + 1 ? cscale(h.ph, h.head) : cscale(L.bd.row[j], h.inv));
     vv[cs] = x;
     if (!a.trans && a.r0 == 0 && cs >= CSK && j > k && j < a.q) a.Hg[(long)k * a.ldh + j] = x;
   }
@@ -558,7 +598,7 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
 #pragma unroll
   for (int rs = RSK; rs < 4; ++rs)
 #pragma unroll
-    for (int cs = CSK; cs < 8; ++cs) X[rs][cs] = csub(X[rs][cs], cmul(zp[rs], cconj(vv[cs])));
+    for (int cs = CSK; cs < 8; ++cs) cfms_conj(X[rs][cs], zp[rs], vv[cs]);
 }
 
 template <int KS>
@@ -577,12 +617,44 @@ __device__ __forceinline__ void bd_phase(double2 (&X)[4][8], const BdArgs& a, Ga
 // transformation through the reflectors.  Output: L.sig[0..keep) descending,
 // v.W rows = kept rows of W^H (n wide), L.sdisc.  Returns keep, or -1 if the
 // vectors could not be certified (the caller then uses the Jacobi path).
-// Requires min(m, n) <= kQB, max(m, n) <= ws, D <= kKB.
-__device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double cutoff, int ws, long long* tcyc) {
+// Requires min(m, n) <= kQB, max(m, n) <= ws, D <= kKB.  The four steps are
+// separate functions; each starts and ends with every thread in step.
+struct SvdShape {
+  int m, nn, p, q, D, ws;
+  bool trans;
+  double cutoff;
+};
+
+// Values that are the same in every lane, moved to scalar registers so that
+// conditions on them compile to uniform branches (function arguments arrive in
+// vector registers and would otherwise count as divergent).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni(double x) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
+__device__ __forceinline__ SvdShape svd_shape(int m, int nn, int D, double cutoff, int ws) {
+  SvdShape sh;
+  sh.m = uni(m);
+  sh.nn = uni(nn);
+  sh.D = uni(D);
+  sh.ws = uni(ws);
+  sh.cutoff = uni(cutoff);
+  sh.trans = sh.m < sh.nn;
+  sh.p = sh.trans ? sh.nn : sh.m;
+  sh.q = sh.trans ? sh.m : sh.nn;
+  return sh;
+}
+
+// Step 1: bidiagonal (L.dc, L.ec) and the reflectors for step 4 (v.H).
+__device__ __noinline__ void svd_bidiag(const SlotView& v, GateLds& L, const SvdShape& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool trans = m < nn;
-  const int p = trans ? nn : m, q = trans ? m : nn;
+  const int p = uni(sh.p), q = uni(sh.q), nn = uni(sh.nn);
+  const bool trans = p != uni(sh.m);
+  (void)tid; (void)lane; (void)wave; (void)trans; (void)p; (void)q; (void)nn;
   double2* Hg = v.H;  // reflector k in row k (stride ws)
+  const int ws = uni(sh.ws);
   {
     BdArgs a;
     a.Hg = Hg;
@@ -614,7 +686,18 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
     bd_phase<7>(X, a, L);
   }
   __syncthreads();
-  tcyc[0] = clock64();
+}
+
+// Step 2: kept singular values (L.sig, scaled by 1/L.sgersh), keep count
+// (L.skeep, -1 on failure), discarded weight (L.sdisc) and the split
+// tridiagonal (L.t, L.t2, L.blo/bhi).
+__device__ __noinline__ void svd_values(GateLds& L, const SvdShape& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = uni(sh.p), q = uni(sh.q), nn = uni(sh.nn);
+  const bool trans = p != uni(sh.m);
+  (void)tid; (void)lane; (void)wave; (void)trans; (void)p; (void)q; (void)nn;
+  const int D = uni(sh.D);
+  const double cutoff = uni(sh.cutoff);
   // -- real bidiagonal by diagonal phase scaling; Golub-Kahan tridiagonal t
   if (tid < q) {
     const double2 d = L.dc[tid];
@@ -729,9 +812,19 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
     L.sfail = 0;
   }
   __syncthreads();
-  tcyc[1] = clock64();
-  const int keep = L.skeep;
-  if (keep < 0) return -1;
+}
+
+// Step 3: orthonormal real vectors of the bidiagonal for the kept values in
+// rows 2k + off of L.Z (off = 1 when X = M'^H).  Unscales L.sig.  Returns
+// false if the vectors could not be certified.
+__device__ __noinline__ bool svd_vectors(GateLds& L, const SvdShape& sh, int keep) {
+  keep = uni(keep);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = uni(sh.p), q = uni(sh.q), nn = uni(sh.nn);
+  const bool trans = p != uni(sh.m);
+  (void)tid; (void)lane; (void)wave; (void)trans; (void)p; (void)q; (void)nn;
+  const int nT = 2 * q;
+  const double tscale = L.sgersh;  // singular values = scaled values * tscale
   // -- vectors of T (one lane per kept value): twisted factorisation of T - s I
   // inside the block that holds s.  Column j of Z: D+ pivots, then D- pivots,
   // then the vector.  Rows 2k + off (k < q) of the vector are the bidiagonal's
@@ -762,10 +855,11 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
       }
     }
     double* zc = Z + j;  // element i at zc[i * kZS]
-    double nrm2 = 1.0;
     if (b1 - b0 == 1) {
       zc[b0 * kZS] = 1.0;
     } else {
+      // twisted factorisation T - s I = N_r Delta_r N_r^T with forward pivots
+      // D+, backward pivots D- and twist r = argmin |D+_r + D-_r + s|
       // forward pivots D+
       double dd = -sj;
       zc[b0 * kZS] = dd;
@@ -804,7 +898,6 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
         if (fabs(dpi) < pivmin) dpi = -pivmin;
         z = -(L.t[i] * rcp_nr(dpi)) * z;
         zc[i * kZS] = z;
-        nrm2 += z * z;
       }
       zc[r * kZS] = 1.0;
       z = 1.0;
@@ -813,29 +906,38 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
         if (fabs(dmi) < pivmin) dmi = -pivmin;
         z = -(L.t[i - 1] * rcp_nr(dmi)) * z;
         zc[i * kZS] = z;
-        nrm2 += z * z;
       }
     }
-    const double inv = 1.0 / sqrt(nrm2);
+    // the rows kept (2k + off) hold half of the vector's weight in exact
+    // arithmetic; normalise them directly
+    double h2 = 0.0;
     for (int k = 0; k < q; ++k) {
       const int i = 2 * k + off;
-      zc[i * kZS] = (i >= b0 && i < b1) ? zc[i * kZS] * inv : 0.0;
+      const double x = (i >= b0 && i < b1) ? zc[i * kZS] : 0.0;
+      zc[i * kZS] = x;
+      h2 = fma(x, x, h2);
     }
+    const double inv = h2 > 0.0 ? 1.0 / sqrt(h2) : 0.0;
+    for (int k = 0; k < q; ++k) zc[(2 * k + off) * kZS] *= inv;
   }
   __syncthreads();
   for (int j = tid; j < keep; j += blockDim.x) L.sig[j] *= tscale;  // unscaled singular values
-  // -- CholQR on Y (q x keep): Y(k, j) = Yb[2 k kZS + j]; the Gram matrix
-  // lives in the interleaved rows no longer needed: G(a, c) = Gb[2 a kZS + c]
+  // -- orthonormalisation of Y (q x keep), Y(k, j) = Yb[2 k kZS + j].  The
+  // Gram matrix G = Y^T Y lives in the interleaved rows no longer needed:
+  // G(a, c) = Gb[2 a kZS + c], a second partial sum in rows 128 + 2 a.  When
+  // max |G - I| <= 1e-3 the columns are refined by Newton-Schulz steps towards
+  // the orthogonal polar factor, Y <- Y (3 I - G) / 2 (the error squares at
+  // every step); otherwise by a Cholesky QR pass.  Stops once max |G - I| is
+  // at rounding level.
   double* Yb = Z + off * kZS;
   double* Gb = Z + (1 - off) * kZS;
-  for (int pass = 0; pass < 2; ++pass) {
-    if (tid == 0) L.serr = 0ull;
-    __syncthreads();
+  double* Gb2 = Gb + 128 * kZS;
+  for (int it = 0; it < 6; ++it) {
     {
-      // lower triangle in 4 x 4 tiles; lanes l and l ^ 32 split the rows of Y
-      const int tile = (wave << 5) | (lane & 31), half = lane >> 5;
+      // 4 x 4 tiles of the full Gram matrix; waves 0-3 and 4-7 split the rows of Y
+      const int tile = tid & 255, half = tid >> 8;
       const int ta = tile >> 4, tc = tile & 15;
-      const bool act = 4 * ta < keep && tc <= ta;
+      const bool act = 4 * ta < keep && 4 * tc < keep;
       double acc[4][4] = {};
       if (act) {
         const int kh = (q + 1) >> 1;
@@ -853,48 +955,87 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
 #pragma unroll
             for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], yc[w], acc[u][w]);
         }
+        double* G = half ? Gb2 : Gb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) G[(long)(2 * (4 * ta + u)) * kZS + 4 * tc + w] = acc[u][w];
       }
+    }
+    __syncthreads();
+    {
+      // G = G1 + G2; err = max |G - I|; Gb <- 3/2 I - G/2 is kept for the refinement
+      double err = 0.0;
+      for (int e = tid; e < keep * keep; e += blockDim.x) {
+        const int ra = e / keep, rc = e - ra * keep;
+        const long o = (long)(2 * ra) * kZS + rc;
+        const double g = Gb[o] + Gb2[o];
+        const double d = g - (ra == rc ? 1.0 : 0.0);
+        err = fmax(err, fabs(d));
+        Gb2[o] = g;
+        Gb[o] = (ra == rc ? 1.0 : 0.0) - 0.5 * d;
+      }
+      if (!(err <= 1e300)) err = 1e300;  // NaN or Inf
+      err = wave_max(err);
+      if (lane == 0) L.red[wave] = err;
+    }
+    __syncthreads();
+    double err = L.red[0];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int w = 1; w < 8; ++w) err = fmax(err, L.red[w]);
+    if (err >= 1e300) return false;
+    if (err <= 1e-14) break;  // orthonormal to working precision
+    if (err <= 1e-3) {
+      // Y <- Y C, C = Gb; 4 x 4 output tiles, computed before any is written
+      const int tr = tid >> 4, tc = tid & 15;
+      const bool act = 4 * tr < q && 4 * tc < keep;
+      double acc[4][4] = {};
+      if (act) {
+        for (int e = 0; e < keep; ++e) {
+          double ya[4], cc[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) acc[u][w] = pair_sum32(acc[u][w], acc[u][w]);
-      if (act && half == 0) {
-        double err = 0.0;
+          for (int u = 0; u < 4; ++u) ya[u] = Yb[(long)(2 * (4 * tr + u)) * kZS + e];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) cc[w] = Gb[(long)(2 * e) * kZS + 4 * tc + w];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], cc[w], acc[u][w]);
+        }
+      }
+      __syncthreads();
+      if (act) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
-            const int ra = 4 * ta + u, rc = 4 * tc + w;
-            if (ra < keep && rc <= ra) {
-              Gb[(long)(2 * ra) * kZS + rc] = acc[u][w];
-              err = fmax(err, fabs(acc[u][w] - (ra == rc ? 1.0 : 0.0)));
-            }
+            const int ra = 4 * tr + u, rc = 4 * tc + w;
+            if (ra < q && rc < keep) Yb[(long)(2 * ra) * kZS + rc] = acc[u][w];
           }
-        if (!(err <= 1e300)) err = 1e300;  // NaN or Inf
-        atomicMax(&L.serr, (unsigned long long)__double_as_longlong(err));
       }
+      __syncthreads();
+      // ||I - G||_2 <= keep * err; one step leaves about 0.75 (keep err)^2
+      if (err * keep <= 1e-7) break;
+      continue;
     }
-    __syncthreads();
-    const double err = __longlong_as_double((long long)L.serr);
-    if (err >= 1e300) return -1;
-    if (err <= 1e-14) break;  // orthonormal to working precision
-    // right-looking Cholesky, lower triangle in place; reciprocal diagonal in ldiag
+    // Cholesky QR: G = L L^T (lower triangle of the summed Gram matrix, in Gb2),
+    // reciprocal diagonal in ldiag, then Y <- Y L^{-T}
     for (int jj = 0; jj < keep; ++jj) {
-      const double djj = Gb[(long)(2 * jj) * kZS + jj];
-      if (!(djj > 1e-10) || !isfinite(djj)) return -1;  // the same value in every thread
+      const double djj = Gb2[(long)(2 * jj) * kZS + jj];
+      if (!(djj > 1e-10) || !isfinite(djj)) return false;  // the same value in every thread
       const double rinv = 1.0 / sqrt(djj);
-      for (int ra = jj + 1 + tid; ra < keep; ra += blockDim.x) Gb[(long)(2 * ra) * kZS + jj] *= rinv;
+      for (int ra = jj + 1 + tid; ra < keep; ra += blockDim.x) Gb2[(long)(2 * ra) * kZS + jj] *= rinv;
       if (tid == 0) L.ldiag[jj] = rinv;
       __syncthreads();
       const int rem = keep - jj - 1;
       for (int e = tid; e < rem * rem; e += blockDim.x) {
         const int ra = jj + 1 + e / rem, rc = jj + 1 + e % rem;
-        if (rc <= ra) Gb[(long)(2 * ra) * kZS + rc] -= Gb[(long)(2 * ra) * kZS + jj] * Gb[(long)(2 * rc) * kZS + jj];
+        if (rc <= ra) Gb2[(long)(2 * ra) * kZS + rc] -= Gb2[(long)(2 * ra) * kZS + jj] * Gb2[(long)(2 * rc) * kZS + jj];
       }
       __syncthreads();
     }
-    // Y <- Y L^{-T}: row k solves L x = y; thread (k, s4) holds entries s4 + 4 t
     {
+      // row k of Y solves L x = y; thread (k, s4) holds entries s4 + 4 t
       const int k = tid >> 2, s4 = tid & 3;
       double* yr = Yb + (long)(2 * k) * kZS;
       double y[16];
@@ -910,7 +1051,7 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
 #pragma unroll
           for (int t = 0; t < (c + 3) / 4; ++t) {
             const int e = 4 * t + s4;
-            if (e < c) part = fma(y[t], Gb[(long)(2 * c) * kZS + e], part);
+            if (e < c) part = fma(y[t], Gb2[(long)(2 * c) * kZS + e], part);
           }
           part = quad_sum(part);
           if (s4 == (c & 3)) y[c >> 2] = (y[c >> 2] - part) * L.ldiag[c];
@@ -923,9 +1064,21 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
       }
     }
     __syncthreads();
-    if (err <= 1e-4) break;  // one pass leaves orthogonality at working precision
   }
-  tcyc[2] = clock64();
+  return true;
+}
+
+// Step 4: kept rows of W^H into v.W (keep x nn).
+__device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdShape& sh, int keep) {
+  keep = uni(keep);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int p = uni(sh.p), q = uni(sh.q), nn = uni(sh.nn);
+  const bool trans = p != uni(sh.m);
+  (void)tid; (void)lane; (void)wave; (void)trans; (void)p; (void)q; (void)nn;
+  const int ws = uni(sh.ws);
+  double2* Hg = v.H;
+  const int off = trans ? 1 : 0;
+  double* Yb = L.Z + off * kZS;
   // -- complex vectors of the bidiagonal, then through the reflectors, held in
   // registers: thread (vl, pl) = (lane / 16, lane % 16) of wave w holds vectors
   // j = 8 w + 2 vl + s (s < 2) at positions pl + 16 e (e < 8)
@@ -946,10 +1099,30 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
     // stage the reflectors in LDS, packed: reflector k has len_k entries from st_k
     double2* R = reinterpret_cast<double2*>(L.Z);
     const int kstart = trans ? q - 1 : q - 2;
-    for (int k = wave; k <= kstart; k += 8) {
-      const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
-      const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
-      for (int i = lane; i < len; i += 64) R[ro + i] = Hg[(long)k * ws + st + i];
+    for (int k0 = wave; k0 <= kstart; k0 += 64) {
+      // up to 8 reflectors per wave in flight: issue every load, then write
+      double2 buf[8][2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int k = k0 + 8 * r;
+        const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          buf[r][h] = (k <= kstart && i < len) ? Hg[(long)k * ws + st + i] : cmk(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int k = k0 + 8 * r;
+        const int len = trans ? p - k : q - k - 1;
+        const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          if (k <= kstart && i < len) R[ro + i] = buf[r][h];
+        }
+      }
     }
     __syncthreads();
     for (int k = kstart; k >= 0; --k) {
@@ -964,26 +1137,24 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
       double2 d[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        double2 acc = cmk(0.0, 0.0);
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           if (16 * e + 15 < st || 16 * e >= st + len) continue;  // the same for all lanes
           const double2 uc = u[e], x = Wr[s][e];
-          acc.x = fma(uc.x, x.x, acc.x);
-          acc.x = fma(uc.y, x.y, acc.x);
-          acc.y = fma(uc.x, x.y, acc.y);
-          acc.y = fma(-uc.y, x.x, acc.y);
+          ar = fma(uc.x, x.x, ar);
+          br = fma(uc.y, x.y, br);
+          ai = fma(uc.x, x.y, ai);
+          bi = fma(-uc.y, x.x, bi);
         }
-        acc.x = row16_sum(acc.x);
-        acc.y = row16_sum(acc.y);
-        d[s] = acc;
+        d[s] = cmk(row16_sum(ar + br), row16_sum(ai + bi));
       }
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           if (16 * e + 15 < st || 16 * e >= st + len) continue;
-          Wr[s][e] = csub(Wr[s][e], cmul(u[e], d[s]));
+          cfms(Wr[s][e], u[e], d[s]);
         }
     }
 #pragma unroll
@@ -995,6 +1166,20 @@ __device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double 
       }
   }
   __syncthreads();
+  __syncthreads();
+}
+
+__device__ int svd_bisect(SlotView& v, GateLds& L, int m, int nn, int D, double cutoff, int ws, long long* tcyc) {
+  const SvdShape sh = svd_shape(m, nn, D, cutoff, ws);
+  svd_bidiag(v, L, sh);
+  tcyc[0] = clock64();
+  svd_values(L, sh);
+  tcyc[1] = clock64();
+  const int keep = uni(L.skeep);
+  if (keep < 0) return -1;
+  if (!svd_vectors(L, sh, keep)) return -1;
+  tcyc[2] = clock64();
+  svd_back(v, L, sh, keep);
   return keep;
 }
 
