@@ -51,6 +51,12 @@ enum {
   Q2C_ERR_BUSY = -6     /* the handle is in use by an unfinished operation                  */
 };
 
+/* Precision of an MPS or an energy evaluation.
+ *   Q2C_FP64   complex128 throughout.
+ *   Q2C_MIXED  site tensors, the two-site contraction, the update B_n = M W and
+ *              the transfer sweeps in complex64 with FP32 accumulation; the SVD,
+ *              the renormalisation, the Schmidt values and the energy sum in FP64
+ *              (Sec. IV-B splits the time between the SVD and the contractions). */
 enum { Q2C_FP64 = 0, Q2C_MIXED = 1 };
 
 typedef struct q2c_ctx q2c_ctx;
@@ -120,7 +126,7 @@ int q2c_ctx_destroy(q2c_ctx* ctx);
  * min(2^(n+1), 2^(N-n-1), max_bond).
  *   n_qubits  2..64.
  *   max_bond  1..256 (D).
- *   precision Q2C_FP64 (complex128 throughout) or Q2C_MIXED.
+ *   precision Q2C_FP64 or Q2C_MIXED (see the enum above).
  *   occ       n_qubits bytes, 0 or 1 (site n starts in |occ[n]>). */
 int mps_create(q2c_ctx* ctx, int n_qubits, int max_bond, int precision,
                const uint8_t* occ, mps_state** out);

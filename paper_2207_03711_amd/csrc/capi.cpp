@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -156,8 +157,9 @@ struct Batch {
   int cm = 1;  // largest bond cap
   std::vector<DBuf> bufs;
 
-  Batch(q2c_ctx* ctx, int N, int D, int slots) {
+  Batch(q2c_ctx* ctx, int N, int D, int slots, int precision) {
     auto& b = d;
+    b.mixed = precision == Q2C_MIXED ? 1 : 0;
     b.n_qubits = N;
     b.max_bond = D;
     b.n_slots = slots;
@@ -294,7 +296,7 @@ struct vqe_problem {
   q2c::Problem host;
   q2c::DevProblem dev;
   DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, occ;
-  std::map<std::pair<int, int>, std::unique_ptr<Batch>> batches;  // (D, slots)
+  std::map<std::tuple<int, int, int>, std::unique_ptr<Batch>> batches;  // (D, slots, precision)
   DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi;
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
          phi_cap = 0;
@@ -310,7 +312,7 @@ void ensure(q2c_ctx* ctx, DBuf& buf, size_t& cap, size_t bytes) {
 
 // Runs n_slots circuits of problem p with theta (n_slots x n_params) and
 // optional per-slot shifts; writes per-slot energies.
-void run_circuits(vqe_problem* p, int D, const double* theta, int n_slots, const int* shift_rot,
+void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int n_slots, const int* shift_rot,
                   const double* shift_val, double* energies, std::vector<double>& stats_out, PhaseTimes& pt) {
   Events ev;
   q2c_ctx* ctx = p->ctx;
@@ -318,8 +320,8 @@ void run_circuits(vqe_problem* p, int D, const double* theta, int n_slots, const
   hipStream_t st = ctx->stream;
   const auto& H = p->host;
   const int np = H.n_params;
-  auto key = std::make_pair(D, n_slots);
-  if (!p->batches.count(key)) p->batches[key] = std::make_unique<Batch>(ctx, H.n_qubits, D, n_slots);
+  auto key = std::make_tuple(D, n_slots, precision);
+  if (!p->batches.count(key)) p->batches[key] = std::make_unique<Batch>(ctx, H.n_qubits, D, n_slots, precision);
   Batch& B = *p->batches[key];
   q2c::DevBatch db = B.d;
 
@@ -413,7 +415,6 @@ void check_eval(const vqe_problem* p, int max_bond, int precision) {
   if (!p->ctx) throw ArgError("problem was compiled without a context (host-only)");
   require(max_bond >= 1 && max_bond <= 256, "max_bond must be in 1..256");
   require(precision == Q2C_FP64 || precision == Q2C_MIXED, "unknown precision");
-  if (precision == Q2C_MIXED) throw ArgError("Q2C_MIXED is not implemented in this build");
 }
 
 int chunk_slots(const vqe_problem* p) { return std::max(1, p->ctx->opts.slots); }
@@ -479,15 +480,14 @@ int mps_create(q2c_ctx* ctx, int n_qubits, int max_bond, int precision, const ui
     require(n_qubits >= 2 && n_qubits <= q2c::kMaxQubits, "n_qubits must be in 2..64");
     require(max_bond >= 1 && max_bond <= 256, "max_bond must be in 1..256");
     require(precision == Q2C_FP64 || precision == Q2C_MIXED, "unknown precision");
-    if (precision == Q2C_MIXED) throw ArgError("Q2C_MIXED is not implemented in this build");
-    for (int i = 0; i < n_qubits; ++i) require(occ[i] <= 1, "occ entries must be 0 or 1");
+      for (int i = 0; i < n_qubits; ++i) require(occ[i] <= 1, "occ entries must be 0 or 1");
     ctx->activate();
     auto s = std::make_unique<mps_state>();
     s->ctx = ctx;
     s->n = n_qubits;
     s->D = max_bond;
     s->precision = precision;
-    s->batch = std::make_unique<Batch>(ctx, n_qubits, max_bond, 1);
+    s->batch = std::make_unique<Batch>(ctx, n_qubits, max_bond, 1, precision);
     s->occ = DBuf(ctx, n_qubits);
     s->gsite = DBuf(ctx, sizeof(int));
     s->grot = DBuf(ctx, sizeof(int));
@@ -580,11 +580,19 @@ int mps_export(mps_state* s, int* chi_out, double* tensors, double* lambdas) {
     const q2c::DevBatch& b = s->batch->d;
     const int N = s->n;
     std::vector<double2> sites(b.site_stride);
+    std::vector<float2> sites32(b.mixed ? b.site_stride : 0);
     std::vector<double> lam(b.lam_stride);
     hip_check(hipMemcpyAsync(chi_out, b.chi, sizeof(int) * (N + 1), hipMemcpyDeviceToHost, st), "copy");
-    hip_check(hipMemcpyAsync(sites.data(), b.sites, sizeof(double2) * b.site_stride, hipMemcpyDeviceToHost, st), "copy");
+    if (b.mixed)
+      hip_check(hipMemcpyAsync(sites32.data(), b.sites, sizeof(float2) * b.site_stride, hipMemcpyDeviceToHost, st),
+                "copy");
+    else
+      hip_check(hipMemcpyAsync(sites.data(), b.sites, sizeof(double2) * b.site_stride, hipMemcpyDeviceToHost, st),
+                "copy");
     hip_check(hipMemcpyAsync(lam.data(), b.lam, sizeof(double) * b.lam_stride, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
+    if (b.mixed)
+      for (long i = 0; i < b.site_stride; ++i) sites[i] = make_double2(sites32[i].x, sites32[i].y);
     if (tensors) {
       size_t o = 0;
       for (int n = 0; n < N; ++n) {
@@ -765,7 +773,7 @@ int vqe_energy(vqe_problem* p, const double* theta, int n_theta, int max_bond, i
     std::vector<double> st;
     PhaseTimes pt;
     double e = 0.0;
-    run_circuits(p, max_bond, theta, 1, nullptr, nullptr, &e, st, pt);
+    run_circuits(p, max_bond, precision, theta, 1, nullptr, nullptr, &e, st, pt);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *energy = e;
     fill_stats(stats, st, 1, secs, pt);
@@ -785,7 +793,7 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
     const int chunk = chunk_slots(p);
     for (int b0 = 0; b0 < n_batch; b0 += chunk) {
       const int nb = std::min(chunk, n_batch - b0);
-      run_circuits(p, max_bond, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st, pt);
+      run_circuits(p, max_bond, precision, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st, pt);
       all_st.insert(all_st.end(), st.begin(), st.end());
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -795,7 +803,7 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
 }
 
 namespace {
-void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond, int precision,
                     std::vector<double>& ep, std::vector<double>& em, double* base, std::vector<double>& all_st,
                     PhaseTimes& pt) {
   // circuits: (rot, +pi/2), (rot, -pi/2) for each listed rotation, then the base circuit if requested
@@ -819,7 +827,7 @@ void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>&
   for (int b0 = 0; b0 < total; b0 += chunk) {
     const int nb = std::min(chunk, total - b0);
     for (int i = 0; i < nb; ++i) std::copy(theta, theta + np, th.begin() + size_t(i) * np);
-    run_circuits(p, max_bond, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st, pt);
+    run_circuits(p, max_bond, precision, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st, pt);
     all_st.insert(all_st.end(), st.begin(), st.end());
   }
   ep.resize(rots.size());
@@ -845,7 +853,7 @@ int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int ma
     std::vector<double> ep, em, all_st;
     PhaseTimes pt;
     double base = 0.0;
-    shift_energies(p, theta, rots, max_bond, ep, em, energy ? &base : nullptr, all_st, pt);
+    shift_energies(p, theta, rots, max_bond, precision, ep, em, energy ? &base : nullptr, all_st, pt);
     std::vector<double> g(n_theta, 0.0);
     for (size_t m = 0; m < R.size(); ++m) g[R[m].param] += -2.0 * R[m].c * 0.5 * (ep[m] - em[m]);
     std::copy(g.begin(), g.end(), grad);
@@ -867,7 +875,7 @@ int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const i
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<double> ep, em, all_st;
     PhaseTimes pt;
-    shift_energies(p, theta, rots, max_bond, ep, em, nullptr, all_st, pt);
+    shift_energies(p, theta, rots, max_bond, precision, ep, em, nullptr, all_st, pt);
     std::copy(ep.begin(), ep.end(), e_plus);
     std::copy(em.begin(), em.end(), e_minus);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

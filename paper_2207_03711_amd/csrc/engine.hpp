@@ -34,6 +34,7 @@ struct DevBatch {
   int max_bond = 0;
   int n_slots = 0;
   int ws = 0;                 // workspace matrix dimension: 2 * largest bond cap
+  int mixed = 0;              // 1: site tensors, contractions and sweeps in complex64
   int cap[kMaxQubits + 1];    // cap[b+1] = capacity of bond b, b = -1..N-1
   long site_off[kMaxQubits + 1];  // offsets (in double2) of site tensors; [N] = total
   long lam_off[kMaxQubits + 1];   // offsets (in doubles) of bond b at lam_off[b]; [N-1] = total

@@ -29,6 +29,30 @@ __device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
 }
 __device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 
+// complex64 counterparts (mixed-precision path: site tensors, contractions and
+// transfer sweeps in FP32 with FP32 accumulation)
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
+template <typename T>
+__device__ __forceinline__ T cval(double r, double i);
+template <>
+__device__ __forceinline__ double2 cval<double2>(double r, double i) { return make_double2(r, i); }
+template <>
+__device__ __forceinline__ float2 cval<float2>(double r, double i) { return make_float2(float(r), float(i)); }
+template <typename T>
+__device__ __forceinline__ T cfrom(double2 a) { return cval<T>(a.x, a.y); }
+__device__ __forceinline__ double2 c64(double2 a) { return a; }
+__device__ __forceinline__ double2 c64(float2 a) { return make_double2(double(a.x), double(a.y)); }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -51,45 +75,44 @@ __device__ double block_sum(double v, double* red) {
 // op(A)[i][k] = TA ? conj(A[k*lda+i]) : A[i*lda+k]
 // op(B)[k][j] = TB ? conj(B[j*ldb+k]) : B[k*ldb+j]
 // lds: 2*64*8 double2.  All threads of the block must call it.
-template <bool TA, bool TB>
-__device__ void bgemm(int M, int N, int K, const double2* __restrict__ A, int lda,
-                      const double2* __restrict__ B, int ldb, double2* __restrict__ C, int ldc,
-                      double2 alpha, bool accumulate, double2* lds) {
+template <bool TA, bool TB, typename T>
+__device__ void bgemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
+                      T* __restrict__ C, int ldc, T alpha, bool accumulate, T* lds) {
   constexpr int BM = 64, BN = 64, BK = 8;
-  double2* As = lds;
-  double2* Bs = lds + BK * BM;
+  T* As = lds;
+  T* Bs = lds + BK * BM;
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;  // 16 x 32 threads
   __syncthreads();
   for (int i0 = 0; i0 < M; i0 += BM) {
     for (int j0 = 0; j0 < N; j0 += BN) {
-      double2 acc[2][4];
+      T acc[2][4];
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] = cmk(0.0, 0.0);
+        for (int q = 0; q < 4; ++q) acc[r][q] = cval<T>(0.0, 0.0);
       for (int k0 = 0; k0 < K; k0 += BK) {
         {
           const int r = tid >> 3, k = tid & 7;
           const int gi = i0 + r, gk = k0 + k;
-          double2 v = cmk(0.0, 0.0);
+          T v = cval<T>(0.0, 0.0);
           if (gi < M && gk < K) v = TA ? cconj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
           As[k * BM + r] = v;
         }
         {
           const int k = tid >> 6, c = tid & 63;
           const int gk = k0 + k, gj = j0 + c;
-          double2 v = cmk(0.0, 0.0);
+          T v = cval<T>(0.0, 0.0);
           if (gk < K && gj < N) v = TB ? cconj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
           Bs[k * BN + c] = v;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < BK; ++k) {
-          const double2 a0 = As[k * BM + ty * 2], a1 = As[k * BM + ty * 2 + 1];
+          const T a0 = As[k * BM + ty * 2], a1 = As[k * BM + ty * 2 + 1];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const double2 bv = Bs[k * BN + tx * 4 + q];
+            const T bv = Bs[k * BN + tx * 4 + q];
             cfma(acc[0][q], a0, bv);
             cfma(acc[1][q], a1, bv);
           }
@@ -102,8 +125,8 @@ __device__ void bgemm(int M, int N, int K, const double2* __restrict__ A, int ld
         for (int q = 0; q < 4; ++q) {
           const int gi = i0 + ty * 2 + r, gj = j0 + tx * 4 + q;
           if (gi < M && gj < N) {
-            double2 v = cmul(alpha, acc[r][q]);
-            double2* dst = &C[(long)gi * ldc + gj];
+            T v = cmul(alpha, acc[r][q]);
+            T* dst = &C[(long)gi * ldc + gj];
             *dst = accumulate ? cadd(*dst, v) : v;
           }
         }
@@ -150,16 +173,17 @@ __device__ void wave_householder(const double2* x, int L, bool rowform, double2*
 
 // ---------------------------------------------------------- init / angles --
 
+template <typename S>
 __global__ void k_init_product(DevBatch b, const uint8_t* occ) {
   const int slot = blockIdx.x;
   const int N = b.n_qubits;
-  double2* sites = b.sites + slot * b.site_stride;
+  S* sites = reinterpret_cast<S*>(b.sites + slot * b.site_stride);  // slot bases as in slot_view
   for (int n = threadIdx.x; n < N; n += blockDim.x) {
-    double2* B = sites + b.site_off[n];
+    S* B = sites + b.site_off[n];
     const int o = occ[n] ? 1 : 0;
     // chi_l = chi_r = 1: element [0][i][0] at i * cap_r
-    B[0] = cmk(o == 0 ? 1.0 : 0.0, 0.0);
-    B[b.cap[n + 1]] = cmk(o == 1 ? 1.0 : 0.0, 0.0);
+    B[0] = cval<S>(o == 0 ? 1.0 : 0.0, 0.0);
+    B[b.cap[n + 1]] = cval<S>(o == 1 ? 1.0 : 0.0, 0.0);
   }
   for (int i = threadIdx.x; i <= N; i += blockDim.x) b.chi[slot * (N + 1) + i] = 1;
   for (int n = threadIdx.x; n < N - 1; n += blockDim.x) b.lam[slot * b.lam_stride + b.lam_off[n]] = 1.0;
@@ -400,34 +424,39 @@ __device__ __forceinline__ HhScalars hh_scalars(double n2, double2 x0) {
 }
 
 // ---- Phase A: Theta = B_n B_{n+1}, gate mixing (Eq. 7), lambda scaling (Eq. 8)
+// S = double2 (FP64 path) or float2 (mixed path: Theta and M in complex64; M'
+// for the SVD always in FP64).
+template <typename S>
 __device__ void gate_contract(const DevBatch& b, SlotView& v, GateLds& L, int n, int chil, int chim, int chir) {
   const int tid = threadIdx.x;
   const int nn = 2 * chir, m = 2 * chil;
   const int capl_r = b.cap[n + 1], capr_r = b.cap[n + 2];
-  const double2* Bn = v.sites + b.site_off[n];
-  const double2* Bn1 = v.sites + b.site_off[n + 1];
+  const S* sites = reinterpret_cast<const S*>(v.sites);
+  const S* Bn = sites + b.site_off[n];
+  const S* Bn1 = sites + b.site_off[n + 1];
+  S* Mw = reinterpret_cast<S*>(v.M);
   for (int j = 0; j < 2; ++j)
-    bgemm<false, false>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, v.M + j * chir, nn,
-                        cmk(1.0, 0.0), false, L.gemm);
+    bgemm<false, false, S>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, Mw + j * chir, nn,
+                           cval<S>(1.0, 0.0), false, reinterpret_cast<S*>(L.gemm));
   double part = 0.0;
   for (int idx = tid; idx < chil * chir; idx += blockDim.x) {
     const int a = idx / chir, c = idx - a * chir;
-    double2 t[4];
+    S t[4];
 #pragma unroll
     for (int ip = 0; ip < 2; ++ip)
 #pragma unroll
-      for (int jp = 0; jp < 2; ++jp) t[2 * ip + jp] = v.M[(long)(2 * a + ip) * nn + jp * chir + c];
+      for (int jp = 0; jp < 2; ++jp) t[2 * ip + jp] = Mw[(long)(2 * a + ip) * nn + jp * chir + c];
     const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + a];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
-        double2 s = cmk(0.0, 0.0);
+        S s = cval<S>(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cfma(s, L.O[(2 * i + jj) * 4 + q], t[q]);
+        for (int q = 0; q < 4; ++q) cfma(s, cfrom<S>(L.O[(2 * i + jj) * 4 + q]), t[q]);
         const long off = (long)(2 * a + i) * nn + jj * chir + c;
-        v.M[off] = s;
-        const double2 sp = cscale(s, la);
+        Mw[off] = s;
+        const double2 sp = cscale(c64(s), la);
         v.A[off] = sp;
         part += cabs2(sp);
       }
@@ -438,12 +467,14 @@ __device__ void gate_contract(const DevBatch& b, SlotView& v, GateLds& L, int n,
 }
 
 // M' = lambda * M again (before the Jacobi fallback).
+template <typename S>
 __device__ void restore_mprime(const DevBatch& b, SlotView& v, int n, int chil, int chir) {
   const int nn = 2 * chir;
+  const S* Mw = reinterpret_cast<const S*>(v.M);
   for (int idx = threadIdx.x; idx < 2 * chil * nn; idx += blockDim.x) {
     const int row = idx / nn;
     const double la = n == 0 ? 1.0 : v.lam[b.lam_off[n - 1] + (row >> 1)];
-    v.A[idx] = cscale(v.M[idx], la);
+    v.A[idx] = cscale(c64(Mw[idx]), la);
   }
   __syncthreads();
 }
@@ -1379,7 +1410,7 @@ __device__ int svd_jacobi(const DevBatch& b, SlotView& v, GateLds& L, int m, int
 
 // kSmall: every bond <= 64 (two-site matrices <= 128 x 128): bisection SVD
 // with a compact Jacobi fallback.  Otherwise: Jacobi with rows up to 512.
-template <bool kSmall>
+template <bool kSmall, typename S>
 __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restrict__ gsite,
                                                   const int* __restrict__ grot, const double2* __restrict__ gpre,
                                                   const double2* __restrict__ gpost, const double* __restrict__ phi_all,
@@ -1418,7 +1449,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     __syncthreads();
     long long tc[8];
     tc[0] = clock64();
-    gate_contract(b, v, L, n, chil, chim, chir);
+    gate_contract<S>(b, v, L, n, chil, chim, chir);
     tc[1] = clock64();
 
     int keep = -1, sweeps = 0;
@@ -1429,7 +1460,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
       keep = svd_bisect(v, L, m, nn, b.max_bond, sp.cutoff_rel, b.ws, tb);
       if (keep < 0) {
         fell_back = true;
-        restore_mprime(b, v, n, chil, chir);
+        restore_mprime<S>(b, v, n, chil, chir);
       }
     }
     if (keep < 0) keep = svd_jacobi<kSmall ? 2 : 8>(b, v, L, m, nn, sp, &sweeps, &conv, tb);
@@ -1446,8 +1477,8 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
 
     // ---- Phase C: truncate (Eq. 9), update (Eq. 10)
     const int capl_r = b.cap[n + 1], capr_r = b.cap[n + 2];
-    double2* Bn = v.sites + b.site_off[n];
-    double2* Bn1 = v.sites + b.site_off[n + 1];
+    S* Bn = reinterpret_cast<S*>(v.sites) + b.site_off[n];
+    S* Bn1 = reinterpret_cast<S*>(v.sites) + b.site_off[n + 1];
     if (tid == 0) {
       double kept = 0.0;
       for (int k = 0; k < keep; ++k) kept += L.sig[k] * L.sig[k];
@@ -1472,12 +1503,22 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     for (int idx = tid; idx < keep * nn; idx += blockDim.x) {
       const int k = idx / nn, col = idx - k * nn;
       const int jj = col / chir, c = col - jj * chir;
-      Bn1[(long)(2 * k + jj) * capr_r + c] = v.W[idx];
+      Bn1[(long)(2 * k + jj) * capr_r + c] = cfrom<S>(v.W[idx]);
     }
     for (int k = tid; k < keep; k += blockDim.x) v.lam[b.lam_off[n] + k] = L.sig[k] / nrm;
     __syncthreads();
     // B_n = M W / ||S_kept||  (Eq. 10: no division by Schmidt values)
-    bgemm<false, true>(m, keep, nn, v.M, nn, v.W, nn, Bn, capl_r, cmk(1.0 / nrm, 0.0), false, L.gemm);
+    if constexpr (sizeof(S) == sizeof(double2)) {
+      bgemm<false, true, S>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, reinterpret_cast<const S*>(v.W), nn, Bn,
+                            capl_r, cval<S>(1.0 / nrm, 0.0), false, reinterpret_cast<S*>(L.gemm));
+    } else {
+      // mixed path: the kept rows of W^H rounded to complex64 (reflector scratch), then M W in FP32
+      S* Wf = reinterpret_cast<S*>(v.H);
+      for (int idx = tid; idx < keep * nn; idx += blockDim.x) Wf[idx] = cfrom<S>(v.W[idx]);
+      __syncthreads();
+      bgemm<false, true, S>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, Wf, nn, Bn, capl_r,
+                            cval<S>(1.0 / nrm, 0.0), false, reinterpret_cast<S*>(L.gemm));
+    }
     if (tid == 0) {
       v.chi[n + 1] = keep;
       const long long te = clock64();
@@ -1495,60 +1536,62 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
 // ----------------------------------------------------------- environments --
 
 // L[0] = 1; L[k+1] = sum_i B_i^H L[k] B_i.   Rt[N] = 1; Rt[k] = sum_i B_i Rt[k+1] B_i^H.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_envs(DevBatch b) {
-  __shared__ double2 lds_gemm[2 * 64 * 8];
+  __shared__ S lds_gemm[2 * 64 * 8];
   const int slot = blockIdx.x;
   const int N = b.n_qubits;
   SlotView v = slot_view(b, slot);
-  double2* L = b.envL + slot * b.env_stride;
-  double2* R = b.envR + slot * b.env_stride;
-  double2* X = v.M;  // scratch
+  S* L = reinterpret_cast<S*>(b.envL + slot * b.env_stride);
+  S* R = reinterpret_cast<S*>(b.envR + slot * b.env_stride);
+  S* X = reinterpret_cast<S*>(v.M);  // scratch
   if (threadIdx.x == 0) {
-    L[b.env_off[0]] = cmk(1.0, 0.0);
-    R[b.env_off[N]] = cmk(1.0, 0.0);
+    L[b.env_off[0]] = cval<S>(1.0, 0.0);
+    R[b.env_off[N]] = cval<S>(1.0, 0.0);
   }
   __syncthreads();
   for (int k = 0; k < N; ++k) {
     const int cl = v.chi[k], cr = v.chi[k + 1];
     const int capl = b.cap[k], capr = b.cap[k + 1];
-    const double2* Bk = v.sites + b.site_off[k];
+    const S* Bk = reinterpret_cast<const S*>(v.sites) + b.site_off[k];
     for (int i = 0; i < 2; ++i) {
-      bgemm<false, false>(cl, cr, cl, L + b.env_off[k], capl, Bk + i * capr, 2 * capr, X, cr, cmk(1.0, 0.0),
+      bgemm<false, false, S>(cl, cr, cl, L + b.env_off[k], capl, Bk + i * capr, 2 * capr, X, cr, cval<S>(1.0, 0.0),
                           false, lds_gemm);
-      bgemm<true, false>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cr, L + b.env_off[k + 1], capr,
-                         cmk(1.0, 0.0), i == 1, lds_gemm);
+      bgemm<true, false, S>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cr, L + b.env_off[k + 1], capr,
+                         cval<S>(1.0, 0.0), i == 1, lds_gemm);
     }
   }
   for (int k = N - 1; k >= 0; --k) {
     const int cl = v.chi[k], cr = v.chi[k + 1];
     const int capl = b.cap[k], capr = b.cap[k + 1];
-    const double2* Bk = v.sites + b.site_off[k];
+    const S* Bk = reinterpret_cast<const S*>(v.sites) + b.site_off[k];
     for (int i = 0; i < 2; ++i) {
-      bgemm<false, false>(cl, cr, cr, Bk + i * capr, 2 * capr, R + b.env_off[k + 1], capr, X, cr, cmk(1.0, 0.0),
+      bgemm<false, false, S>(cl, cr, cr, Bk + i * capr, 2 * capr, R + b.env_off[k + 1], capr, X, cr, cval<S>(1.0, 0.0),
                           false, lds_gemm);
-      bgemm<false, true>(cl, cl, cr, X, cr, Bk + i * capr, 2 * capr, R + b.env_off[k], capl, cmk(1.0, 0.0),
+      bgemm<false, true, S>(cl, cl, cr, X, cr, Bk + i * capr, 2 * capr, R + b.env_off[k], capl, cval<S>(1.0, 0.0),
                          i == 1, lds_gemm);
     }
   }
-  if (threadIdx.x == 0) v.stats[kStatNorm] = L[b.env_off[N]].x;
+  if (threadIdx.x == 0) v.stats[kStatNorm] = double(L[b.env_off[N]].x);
 }
 
 // --------------------------------------------------------- Pauli sweeps ---
 
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __restrict__ sx,
                                                   const uint64_t* __restrict__ sz, int n_strings,
                                                   double2* scratch, int cm, double* ev_re, double* ev_im) {
-  __shared__ double2 lds_gemm[2 * 64 * 8];
+  __shared__ S lds_gemm[2 * 64 * 8];
   __shared__ double red[kBlock / 64];
   const int slot = blockIdx.y;
   const int N = b.n_qubits;
   SlotView v = slot_view(b, slot);
-  const double2* L = b.envL + slot * b.env_stride;
-  const double2* R = b.envR + slot * b.env_stride;
-  double2* T0 = scratch + ((long)slot * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
-  double2* T1 = T0 + (long)cm * cm;
-  double2* X = T1 + (long)cm * cm;
-  const double nrm = L[b.env_off[N]].x;
+  const S* L = reinterpret_cast<const S*>(b.envL + slot * b.env_stride);
+  const S* R = reinterpret_cast<const S*>(b.envR + slot * b.env_stride);
+  S* T0 = reinterpret_cast<S*>(scratch) + ((long)slot * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
+  S* T1 = T0 + (long)cm * cm;
+  S* X = T1 + (long)cm * cm;
+  const double nrm = double(L[b.env_off[N]].x);
   for (int s = blockIdx.x; s < n_strings; s += gridDim.x) {
     const uint64_t x = sx[s], z = sz[s];
     const uint64_t mk = x | z;
@@ -1558,39 +1601,39 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
     } else {
       const int lo = __builtin_ctzll(mk), hi = 63 - __builtin_clzll(mk);
       const int c0 = v.chi[lo];
-      const double2* Llo = L + b.env_off[lo];
+      const S* Llo = L + b.env_off[lo];
       for (int idx = threadIdx.x; idx < c0 * c0; idx += blockDim.x) {
         const int a = idx / c0, c = idx - a * c0;
         T0[(long)a * cm + c] = Llo[(long)a * b.cap[lo] + c];
       }
       __syncthreads();
-      double2* T = T0;
-      double2* Tn = T1;
+      S* T = T0;
+      S* Tn = T1;
       for (int k = lo; k <= hi; ++k) {
         const int cl = v.chi[k], cr = v.chi[k + 1];
         const int capr = b.cap[k + 1];
-        const double2* Bk = v.sites + b.site_off[k];
+        const S* Bk = reinterpret_cast<const S*>(v.sites) + b.site_off[k];
         const int xb = (x >> k) & 1, zb = (z >> k) & 1;
         for (int i = 0; i < 2; ++i) {
           const int ip = xb ? 1 - i : i;
-          double2 ph = cmk(1.0, 0.0);
-          if (zb && !xb) ph = i == 0 ? cmk(1.0, 0.0) : cmk(-1.0, 0.0);  // Z
-          if (zb && xb) ph = i == 0 ? cmk(0.0, -1.0) : cmk(0.0, 1.0);   // Y: <0|Y|1> = -i
-          bgemm<false, false>(cl, cr, cl, T, cm, Bk + ip * capr, 2 * capr, X, cm, cmk(1.0, 0.0), false, lds_gemm);
-          bgemm<true, false>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1, lds_gemm);
+          S ph = cval<S>(1.0, 0.0);
+          if (zb && !xb) ph = cval<S>(i == 0 ? 1.0 : -1.0, 0.0);  // Z
+          if (zb && xb) ph = cval<S>(0.0, i == 0 ? -1.0 : 1.0);   // Y: <0|Y|1> = -i
+          bgemm<false, false, S>(cl, cr, cl, T, cm, Bk + ip * capr, 2 * capr, X, cm, cval<S>(1.0, 0.0), false, lds_gemm);
+          bgemm<true, false, S>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1, lds_gemm);
         }
-        double2* t = T;
+        S* t = T;
         T = Tn;
         Tn = t;
       }
       // <P> = sum_{c,c'} T[c][c'] R[c][c'],  R[c][c'] = Rt[c'][c]
       const int ch = v.chi[hi + 1];
-      const double2* Rh = R + b.env_off[hi + 1];
+      const S* Rh = R + b.env_off[hi + 1];
       const int ldr = b.cap[hi + 1];
       double pr = 0.0, pi = 0.0;
       for (int idx = threadIdx.x; idx < ch * ch; idx += blockDim.x) {
         const int a = idx / ch, c = idx - a * ch;
-        const double2 p = cmul(T[(long)a * cm + c], Rh[(long)c * ldr + a]);
+        const double2 p = cmul(c64(T[(long)a * cm + c]), c64(Rh[(long)c * ldr + a]));
         pr += p.x;
         pi += p.y;
       }
@@ -1632,7 +1675,10 @@ __global__ void k_energy_reduce(const double* coeff, const double* ev_re, const 
 // --------------------------------------------------------------- launchers --
 
 hipError_t launch_init_product(const DevBatch& b, const uint8_t* d_occ, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_product, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
+  if (b.mixed)
+    hipLaunchKernelGGL(k_init_product<float2>, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
+  else
+    hipLaunchKernelGGL(k_init_product<double2>, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
   return hipGetLastError();
 }
 
@@ -1650,25 +1696,39 @@ hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, 
   if (g1 <= g0) return hipSuccess;
   int cm = 1;
   for (int i = 0; i <= b.n_qubits; ++i) cm = cm > b.cap[i] ? cm : b.cap[i];
-  if (cm <= kKB)
-    hipLaunchKernelGGL(k_gates<true>, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi,
-                       n_rot, g0, g1, sp);
+  const dim3 grid(b.n_slots), block(kBlock);
+  if (cm <= kKB && !b.mixed)
+    hipLaunchKernelGGL((k_gates<true, double2>), grid, block, 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot, g0,
+                       g1, sp);
+  else if (cm <= kKB)
+    hipLaunchKernelGGL((k_gates<true, float2>), grid, block, 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot, g0,
+                       g1, sp);
+  else if (!b.mixed)
+    hipLaunchKernelGGL((k_gates<false, double2>), grid, block, 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot,
+                       g0, g1, sp);
   else
-    hipLaunchKernelGGL(k_gates<false>, dim3(b.n_slots), dim3(kBlock), 0, st, b, d_site, d_rot, d_pre, d_post, b.phi,
-                       n_rot, g0, g1, sp);
+    hipLaunchKernelGGL((k_gates<false, float2>), grid, block, 0, st, b, d_site, d_rot, d_pre, d_post, b.phi, n_rot,
+                       g0, g1, sp);
   return hipGetLastError();
 }
 
 hipError_t launch_envs(const DevBatch& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_envs, dim3(b.n_slots), dim3(kBlock), 0, st, b);
+  if (b.mixed)
+    hipLaunchKernelGGL(k_envs<float2>, dim3(b.n_slots), dim3(kBlock), 0, st, b);
+  else
+    hipLaunchKernelGGL(k_envs<double2>, dim3(b.n_slots), dim3(kBlock), 0, st, b);
   return hipGetLastError();
 }
 
 hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings, double2* d_scratch,
                         int n_wg, int cm, double* d_ev_re, double* d_ev_im, hipStream_t st) {
   if (n_strings == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pauli, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch, cm,
-                     d_ev_re, d_ev_im);
+  if (b.mixed)
+    hipLaunchKernelGGL(k_pauli<float2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch,
+                       cm, d_ev_re, d_ev_im);
+  else
+    hipLaunchKernelGGL(k_pauli<double2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch,
+                       cm, d_ev_re, d_ev_im);
   return hipGetLastError();
 }
 

@@ -368,3 +368,92 @@ def test_q16_d64_energy_full_size(q2c, ctx):
     assert st["max_chi"] == 64
     assert 0.5 < st["discarded_weight_sum"] / ref["discarded_weight_sum"] < 2.0
     p.close()
+
+
+# ---------------------------------------------------------------- mixed path
+# Site tensors, contractions, the update and the transfer sweeps in complex64;
+# SVD, renormalisation and the energy sum in FP64.  Bar: 1e-5 Ha on energies
+# (1e-5 on states) against the FP64 oracle, on runs that are exact (full bond
+# dimension) or whose truncation is well conditioned at FP32 rounding: every
+# cut of the oracle run separates the kept and the dropped Schmidt values by
+# at least 1e-5 s_1.  Runs with closer cuts (8 qubits at D = 3..6 have gaps of
+# 1e-9 s_1 and below) follow different trajectories once values are rounded
+# to FP32; the same happens to the oracle when its site tensors are rounded to
+# complex64, so those runs carry no 1e-5 bar.
+
+
+def test_mixed_random_gates_full_bond(q2c, ctx):
+    rng = np.random.default_rng(21)
+    n, D = 6, 8
+    occ = [int(b) for b in rng.integers(0, 2, n)]
+    g = q2c.MPS(ctx, occ, D, precision=q2c.Q2C_MIXED)
+    o = om.MPS(occ, D)
+    for _ in range(80):
+        site = int(rng.integers(0, n - 1))
+        U = _random_unitary(rng)
+        g.apply_gate(site, U)
+        o.apply_gate(site, U)
+    chi, sites, lams = g.export()
+    assert list(chi[1:-1]) == [o.chi(b) for b in range(n - 1)]
+    psi_g = _gpu_statevector(sites)
+    assert np.max(np.abs(psi_g - o.to_statevector())) < 1e-5
+    assert abs(np.vdot(psi_g, psi_g).real - 1.0) < 1e-5
+    g.close()
+
+
+def test_mixed_pauli_expectations(q2c, ctx):
+    rng = np.random.default_rng(12)
+    n = 4
+    g = q2c.MPS(ctx, [1, 0, 0, 1], 4, precision=q2c.Q2C_MIXED)
+    o = om.MPS([1, 0, 0, 1], 4)
+    for _ in range(20):
+        site = int(rng.integers(0, n - 1))
+        U = _random_unitary(rng)
+        g.apply_gate(site, U)
+        o.apply_gate(site, U)
+    xs = np.array([x for x in range(16) for z in range(16)], dtype=np.uint64)
+    zs = np.array([z for x in range(16) for z in range(16)], dtype=np.uint64)
+    re, im = g.expect(xs, zs)
+    want = om.pauli_expectations(o, list(zip(xs.tolist(), zs.tolist())))
+    assert np.max(np.abs(re - want.real)) < 1e-5
+    assert np.max(np.abs(im - want.imag)) < 1e-5
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["h2_d4", "q6_d8", "q8_d16", "q8_d8", "q8_d2"])
+def test_mixed_energy_within_1e5(q2c, ctx, case):
+    if case.startswith("h2"):
+        I = h2_like_integrals()
+        th = np.array([0.0, 0.0, 0.31])
+    elif case.startswith("q8"):
+        I, th = CONFIGS["q8_d16"].integrals(), CONFIGS["q8_d16"].theta()
+    else:
+        I = random_integrals(3, 3 - 1, 43)
+        th = random_theta(n_uccsd_params(I.n_orb, I.n_elec), 53)
+    D = int(case.split("_d")[1])
+    p = _problem(q2c, ctx, I)
+    e64, _ = p.energy(th, D)
+    e32, st = p.energy(th, D, precision=q2c.Q2C_MIXED)
+    e_ref, spread, (n, c_id, terms, rots, phis, occ) = _oracle_energy(I, th, D)
+    assert spread <= WELL_CONDITIONED
+    m = om.run_circuit(n, occ, uccsd.compile_fused(n, I.n_elec)[1], phis, D)
+    assert m.min_gap_rel >= 1e-5  # well conditioned at FP32 rounding
+    assert abs(e64 - e_ref) < 1e-10
+    assert abs(e32 - e_ref) < 1e-5, (e32, e_ref)
+    assert st["max_abs_imag"] < 1e-5
+    p.close()
+
+
+def test_mixed_batch_equals_single(q2c, ctx):
+    cfg = CONFIGS["q8_d16"]
+    I = cfg.integrals()
+    th = cfg.theta()
+    rng = np.random.default_rng(3)
+    thetas = np.stack([th, th + rng.uniform(-0.05, 0.05, th.shape), th])
+    p = _problem(q2c, ctx, I)
+    eb, _ = p.energy_batch(thetas, 8, precision=q2c.Q2C_MIXED)
+    for k in range(3):
+        e1, _ = p.energy(thetas[k], 8, precision=q2c.Q2C_MIXED)
+        assert abs(eb[k] - e1) < 1e-13
+    assert abs(eb[0] - eb[2]) == 0.0
+    p.close()
