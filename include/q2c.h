@@ -220,6 +220,57 @@ int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const i
                        int n_rot, int max_bond, int precision, double* e_plus, double* e_minus,
                        q2c_stats* stats);
 
+/* ---------------------------------------------------------------- serving
+ * A request server for independent fragment solves (the per-fragment VQE of
+ * the DMET embedding, Sec. III-B; fragments are independent, Sec. III-C).
+ * Requests with the same (qubits, electrons, D, precision) form a class: one
+ * slot batch on the device sharing the UCCSD gate list; every slot carries
+ * its own Hamiltonian, parameters and gate cursor.  q2c_server_step()
+ * retires finished slots, admits queued requests into free slots (creating a
+ * class when the context's HBM budget allows) and launches the next gate
+ * chunk of every class on that class's own stream, so classes overlap on the
+ * device and requests join while others run (continuous batching).  Each
+ * result depends only on its own request: served alone or in any mix it is
+ * bit-for-bit the same as vqe_energy() of the same problem.  Not thread-safe;
+ * one thread drives a server. */
+typedef struct q2c_server q2c_server;
+
+typedef struct {
+  int slots_per_class;  /* slots of each class; default 64                      */
+  int gates_per_step;   /* gates a slot advances per launch; default 1024       */
+} q2c_server_opts;
+
+typedef struct {
+  uint64_t tag;         /* the caller's tag from q2c_server_submit              */
+  int status;           /* Q2C_OK, or the error code that ended the request     */
+  int n_qubits, max_bond, precision;
+  double energy;        /* <psi|H|psi> / <psi|psi> (Eq. 2)                       */
+  double n_frag;        /* sum of <n_p> over the first 2 n_frag_orb spin-orbitals */
+  double submit_s, admit_s, done_s;  /* seconds since the server was created */
+  double discarded_weight_sum;
+  int max_chi;
+} q2c_result;
+
+/* opts nullable (defaults).  The server uses the context's device, budget and
+ * SVD options; it creates one stream per class. */
+int q2c_server_create(q2c_ctx* ctx, const q2c_server_opts* opts, q2c_server** out);
+int q2c_server_destroy(q2c_server* srv);
+
+/* Queue one energy evaluation.  Integrals as for vqe_problem_create (the
+ * problem is compiled here, which counts toward the request's latency);
+ * theta as for vqe_energy; n_frag_orb in 0..n_orb selects the spatial
+ * orbitals whose occupation is returned in n_frag.  Copies every input. */
+int q2c_server_submit(q2c_server* srv, uint64_t tag, int n_orb, int n_elec, const double* h1,
+                      const double* eri, double e_const, const double* theta, int n_theta,
+                      int max_bond, int precision, int n_frag_orb);
+
+/* One scheduling round (does not wait for running launches).  Outputs
+ * nullable: requests still queued, requests on the device, results ready. */
+int q2c_server_step(q2c_server* srv, int* n_queued, int* n_active, int* n_ready);
+
+/* Move up to max_out finished results into out (completion order). */
+int q2c_server_poll(q2c_server* srv, q2c_result* out, int max_out, int* n_out);
+
 /* Thread-local message for the last non-OK return on this thread. */
 const char* q2c_last_error(void);
 

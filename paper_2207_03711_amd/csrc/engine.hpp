@@ -35,6 +35,9 @@ struct DevBatch {
   int n_slots = 0;
   int ws = 0;                 // workspace matrix dimension: 2 * largest bond cap
   int mixed = 0;              // 1: site tensors, contractions and sweeps in complex64
+  int slot0 = 0;              // first slot of a launch (launches cover slots slot0 .. slot0 + n_slots - 1)
+  int* cursor = nullptr;      // optional per-slot next gate: the gate kernel then runs up to
+  int n_gates = 0;            //   g1 - g0 gates from cursor[slot] (capped at n_gates) and advances it
   int cap[kMaxQubits + 1];    // cap[b+1] = capacity of bond b, b = -1..N-1
   long site_off[kMaxQubits + 1];  // offsets (in double2) of site tensors; [N] = total
   long lam_off[kMaxQubits + 1];   // offsets (in doubles) of bond b at lam_off[b]; [N-1] = total

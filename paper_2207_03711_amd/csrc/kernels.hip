@@ -175,7 +175,7 @@ __device__ void wave_householder(const double2* x, int L, bool rowform, double2*
 
 template <typename S>
 __global__ void k_init_product(DevBatch b, const uint8_t* occ) {
-  const int slot = blockIdx.x;
+  const int slot = b.slot0 + blockIdx.x;
   const int N = b.n_qubits;
   S* sites = reinterpret_cast<S*>(b.sites + slot * b.site_stride);  // slot bases as in slot_view
   for (int n = threadIdx.x; n < N; n += blockDim.x) {
@@ -194,13 +194,15 @@ __global__ void k_init_product(DevBatch b, const uint8_t* occ) {
   }
 }
 
+// phi of slots slot0 + y (theta and the shifts are indexed from the launch's first slot)
 __global__ void k_angles(double* phi, int n_rot, const double* rot_c, const int* rot_param,
-                         const double* theta, int n_theta, const int* shift_rot, const double* shift_val) {
-  const int slot = blockIdx.y;
+                         const double* theta, int n_theta, const int* shift_rot, const double* shift_val,
+                         int slot0) {
+  const int r = blockIdx.y, slot = slot0 + r;
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_rot) return;
-  double v = -2.0 * rot_c[m] * theta[(long)slot * n_theta + rot_param[m]];
-  if (shift_rot && shift_rot[slot] == m) v += shift_val[slot];
+  double v = -2.0 * rot_c[m] * theta[(long)r * n_theta + rot_param[m]];
+  if (shift_rot && shift_rot[r] == m) v += shift_val[r];
   phi[(long)slot * n_rot + m] = v;
 }
 
@@ -1416,13 +1418,19 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
                                                   const double2* __restrict__ gpost, const double* __restrict__ phi_all,
                                                   int n_rot, int g0, int g1, SvdParams sp) {
   __shared__ GateLds L;
-  const int slot = blockIdx.x;
+  const int slot = b.slot0 + blockIdx.x;
   const int tid = threadIdx.x;
   SlotView v = slot_view(b, slot);
   const double* phi = phi_all ? phi_all + (long)slot * n_rot : nullptr;
+  if (b.cursor) {
+    // per-slot progress: up to g1 - g0 gates from the slot's cursor
+    const int c = b.cursor[slot];
+    g1 = min(c + (g1 - g0), b.n_gates);
+    g0 = c;
+  }
   if (tid == 0) L.sabort = (*v.flags & kFlagNumeric) ? 1 : 0;
   __syncthreads();
-  if (L.sabort) return;
+  if (L.sabort || g0 >= g1) return;
 
   for (int g = g0; g < g1; ++g) {
     const int n = gsite[g];
@@ -1531,6 +1539,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     }
     __syncthreads();
   }
+  if (b.cursor && tid == 0) b.cursor[slot] = g1;
 }
 
 // ----------------------------------------------------------- environments --
@@ -1539,7 +1548,7 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_envs(DevBatch b) {
   __shared__ S lds_gemm[2 * 64 * 8];
-  const int slot = blockIdx.x;
+  const int slot = b.slot0 + blockIdx.x;
   const int N = b.n_qubits;
   SlotView v = slot_view(b, slot);
   S* L = reinterpret_cast<S*>(b.envL + slot * b.env_stride);
@@ -1583,12 +1592,12 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
                                                   double2* scratch, int cm, double* ev_re, double* ev_im) {
   __shared__ S lds_gemm[2 * 64 * 8];
   __shared__ double red[kBlock / 64];
-  const int slot = blockIdx.y;
+  const int r = blockIdx.y, slot = b.slot0 + r;  // outputs and scratch are indexed from the first slot
   const int N = b.n_qubits;
   SlotView v = slot_view(b, slot);
   const S* L = reinterpret_cast<const S*>(b.envL + slot * b.env_stride);
   const S* R = reinterpret_cast<const S*>(b.envR + slot * b.env_stride);
-  S* T0 = reinterpret_cast<S*>(scratch) + ((long)slot * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
+  S* T0 = reinterpret_cast<S*>(scratch) + ((long)r * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
   S* T1 = T0 + (long)cm * cm;
   S* X = T1 + (long)cm * cm;
   const double nrm = double(L[b.env_off[N]].x);
@@ -1642,8 +1651,8 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
       ev = cmk(pr / nrm, pi / nrm);
     }
     if (threadIdx.x == 0) {
-      ev_re[(long)slot * n_strings + s] = ev.x;
-      ev_im[(long)slot * n_strings + s] = ev.y;
+      ev_re[(long)r * n_strings + s] = ev.x;
+      ev_im[(long)r * n_strings + s] = ev.y;
     }
     __syncthreads();
   }
@@ -1651,8 +1660,8 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
 
 // Neumaier-compensated sum in term order, identity coefficient last.
 __global__ void k_energy_reduce(const double* coeff, const double* ev_re, const double* ev_im, int n_strings,
-                                double c_identity, double* energy, double* stats) {
-  const int slot = blockIdx.x;
+                                double c_identity, double* energy, double* stats, int slot0) {
+  const int r = blockIdx.x, slot = slot0 + r;  // inputs and energy indexed from the first slot
   if (threadIdx.x != 0) return;
   double s = 0.0, comp = 0.0, mi = 0.0;
   auto add = [&](double x) {
@@ -1664,11 +1673,11 @@ __global__ void k_energy_reduce(const double* coeff, const double* ev_re, const 
     s = t;
   };
   for (int i = 0; i < n_strings; ++i) {
-    add(coeff[i] * ev_re[(long)slot * n_strings + i]);
-    mi = fmax(mi, fabs(ev_im[(long)slot * n_strings + i]));
+    add(coeff[i] * ev_re[(long)r * n_strings + i]);
+    mi = fmax(mi, fabs(ev_im[(long)r * n_strings + i]));
   }
   add(c_identity);
-  energy[slot] = s + comp;
+  energy[r] = s + comp;
   stats[slot * kNStats + kStatMaxImag] = mi;
 }
 
@@ -1687,7 +1696,7 @@ hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d
   if (p.n_rot == 0) return hipSuccess;
   dim3 grid((p.n_rot + 255) / 256, b.n_slots);
   hipLaunchKernelGGL(k_angles, grid, dim3(256), 0, st, b.phi, p.n_rot, p.rot_c, p.rot_param, d_theta, n_theta,
-                     d_shift_rot, d_shift_val);
+                     d_shift_rot, d_shift_val, b.slot0);
   return hipGetLastError();
 }
 
@@ -1735,7 +1744,7 @@ hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* 
 hipError_t launch_energy_reduce(const DevBatch& b, const double* d_coeff, const double* d_ev_re, const double* d_ev_im,
                                 int n_strings, double c_identity, double* d_energy, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_reduce, dim3(b.n_slots), dim3(64), 0, st, d_coeff, d_ev_re, d_ev_im, n_strings,
-                     c_identity, d_energy, b.stats);
+                     c_identity, d_energy, b.stats, b.slot0);
   return hipGetLastError();
 }
 

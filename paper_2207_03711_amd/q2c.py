@@ -77,6 +77,30 @@ class q2c_stats(C.Structure):
         return d
 
 
+class q2c_server_opts(C.Structure):
+    _fields_ = [("slots_per_class", C.c_int), ("gates_per_step", C.c_int)]
+
+
+class q2c_result(C.Structure):
+    _fields_ = [
+        ("tag", C.c_uint64),
+        ("status", C.c_int),
+        ("n_qubits", C.c_int),
+        ("max_bond", C.c_int),
+        ("precision", C.c_int),
+        ("energy", C.c_double),
+        ("n_frag", C.c_double),
+        ("submit_s", C.c_double),
+        ("admit_s", C.c_double),
+        ("done_s", C.c_double),
+        ("discarded_weight_sum", C.c_double),
+        ("max_chi", C.c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2207_03711_amd.build`")
@@ -119,6 +143,12 @@ SIGNATURES = {
     "vqe_grad_paramshift": (C.c_int, [_vp, _pd, C.c_int, C.c_int, C.c_int, _pd, _pd, C.POINTER(q2c_stats)]),
     "vqe_shift_energies": (C.c_int, [_vp, _pd, C.c_int, _pi, C.c_int, C.c_int, C.c_int, _pd, _pd,
                                      C.POINTER(q2c_stats)]),
+    "q2c_server_create": (C.c_int, [_vp, C.POINTER(q2c_server_opts), _pvp]),
+    "q2c_server_destroy": (C.c_int, [_vp]),
+    "q2c_server_submit": (C.c_int, [_vp, C.c_uint64, C.c_int, C.c_int, _pd, _pd, C.c_double, _pd, C.c_int, C.c_int,
+                                    C.c_int, C.c_int]),
+    "q2c_server_step": (C.c_int, [_vp, _pi, _pi, _pi]),
+    "q2c_server_poll": (C.c_int, [_vp, C.POINTER(q2c_result), C.c_int, _pi]),
     "q2c_last_error": (C.c_char_p, []),
     "q2c_version": (C.c_char_p, []),
 }
@@ -386,3 +416,66 @@ class MPS:
 
     def stats(self) -> dict:
         return mps_get_stats(self.h)
+
+
+# ------------------------------------------------------------------- serving
+
+
+def q2c_server_create(ctx, opts=None):
+    h = _vp()
+    _check(lib.q2c_server_create(ctx, C.byref(opts) if opts is not None else None, C.byref(h)))
+    return h
+
+
+def q2c_server_destroy(srv):
+    _check(lib.q2c_server_destroy(srv))
+
+
+def q2c_server_submit(srv, tag: int, n_orb: int, n_elec: int, h1, eri, e_const: float, theta, max_bond: int,
+                      precision: int = Q2C_FP64, n_frag_orb: int = 0):
+    h = _f64(h1)
+    e = _f64(eri)
+    t = _f64(theta)
+    _check(lib.q2c_server_submit(srv, tag, n_orb, n_elec, _dp(h), _dp(e), e_const, _dp(t), len(t), max_bond,
+                                 precision, n_frag_orb))
+
+
+def q2c_server_step(srv):
+    q, a, r = C.c_int(), C.c_int(), C.c_int()
+    _check(lib.q2c_server_step(srv, C.byref(q), C.byref(a), C.byref(r)))
+    return q.value, a.value, r.value
+
+
+def q2c_server_poll(srv, max_out: int = 256):
+    buf = (q2c_result * max_out)()
+    n = C.c_int()
+    _check(lib.q2c_server_poll(srv, buf, max_out, C.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+class Server:
+    """Continuous-batching request server (argument marshalling only)."""
+
+    def __init__(self, ctx: Context, slots_per_class: int = 64, gates_per_step: int = 1024):
+        o = q2c_server_opts(slots_per_class, gates_per_step)
+        self.h = q2c_server_create(ctx.h, o)
+
+    def submit(self, tag, n_orb, n_elec, h1, eri, e_const, theta, max_bond, precision=Q2C_FP64, n_frag_orb=0):
+        q2c_server_submit(self.h, tag, n_orb, n_elec, h1, eri, e_const, theta, max_bond, precision, n_frag_orb)
+
+    def step(self):
+        return q2c_server_step(self.h)
+
+    def poll(self, max_out: int = 256):
+        return q2c_server_poll(self.h, max_out)
+
+    def close(self):
+        if self.h:
+            q2c_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

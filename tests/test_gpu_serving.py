@@ -1,0 +1,98 @@
+"""GPU: the request server (continuous batching of fragment solves).
+
+Requests of several classes (qubit count, D, precision) are submitted in two
+waves -- the second while the first is on the device -- into classes with
+fewer slots than requests, so slots are reused.  Every served energy must be
+bit-for-bit the energy of the same problem run alone through vqe_energy, and
+at full bond dimension the energy and the fragment occupation must match the
+state-vector oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import fermion, statevector as sv, uccsd
+from workloads import serving_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q2c():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_03711_amd import q2c as mod
+
+    return mod
+
+
+def _oracle(I, th, k):
+    n = 2 * I.n_orb
+    c_id, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri, I.e_const))
+    rots = uccsd.rotations(n, I.n_elec)
+    pa = sv.PauliApplier(n)
+    psi = sv.evolve(n, uccsd.hf_occupation(n, I.n_elec), rots, uccsd.rotation_angles(rots, th), pa)
+    e = sv.energy(pa, c_id, terms, psi)
+    nf = sum(0.5 * (1.0 - sv.energy(pa, 0.0, [(0, 1 << q, 1.0)], psi)) for q in range(2 * k))
+    return e, nf
+
+
+def test_served_results_equal_alone(q2c):
+    reqs = serving_stream(12, seed=77, k_range=(1, 2), bonds=(2, 4, 16))
+    jobs = [(r.index, r, q2c.Q2C_FP64) for r in reqs] + [(100 + r.index, r, q2c.Q2C_MIXED) for r in reqs[:3]]
+    ctx = q2c.Context(0)
+    srv = q2c.Server(ctx, slots_per_class=3, gates_per_step=64)
+
+    def submit(tag, r, prec):
+        I = r.integrals()
+        srv.submit(tag, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), r.max_bond, prec, r.n_frag_orb)
+
+    for j in jobs[:7]:
+        submit(*j)
+    results, steps, t0 = {}, 0, time.time()
+    while len(results) < len(jobs):
+        q, a, n = srv.step()
+        steps += 1
+        if steps == 3:
+            assert a > 0  # the second wave joins while the first is running
+            for j in jobs[7:]:
+                submit(*j)
+        for res in srv.poll():
+            results[res["tag"]] = res
+        assert time.time() - t0 < 300
+    srv.close()
+
+    for tag, r, prec in jobs:
+        res = results[tag]
+        assert res["status"] == 0
+        assert res["submit_s"] <= res["admit_s"] <= res["done_s"]
+        I, th = r.integrals(), r.theta()
+        p = q2c.Problem(ctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+        e_alone, _ = p.energy(th, r.max_bond, precision=prec)
+        p.close()
+        assert abs(res["energy"] - e_alone) <= 1e-13, (tag, res["energy"], e_alone)
+        n = 2 * I.n_orb
+        if r.max_bond >= 2 ** (n // 2) and prec == q2c.Q2C_FP64:
+            e_ref, nf_ref = _oracle(I, th, r.n_frag_orb)
+            assert abs(res["energy"] - e_ref) < 1e-10
+            assert abs(res["n_frag"] - nf_ref) < 1e-10
+    ctx.close()
+
+
+def test_server_rejects_bad_requests(q2c):
+    ctx = q2c.Context(0)
+    srv = q2c.Server(ctx)
+    r = serving_stream(1, seed=3, k_range=(1, 1), bonds=(4,))[0]
+    I = r.integrals()
+    with pytest.raises(q2c.Q2CError):
+        srv.submit(0, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta()[:-1], 4)  # wrong theta length
+    with pytest.raises(q2c.Q2CError):
+        srv.submit(0, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), 0)  # bad D
+    with pytest.raises(q2c.Q2CError):
+        srv.submit(0, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), 4, n_frag_orb=I.n_orb + 1)
+    assert srv.step() == (0, 0, 0)
+    srv.close()
+    ctx.close()
