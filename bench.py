@@ -99,6 +99,72 @@ def cpu_baseline(cfg, gpu_flops_per_eval, budget_s):
     }
 
 
+def arrival_times(stream, rate):
+    """Arrival time of each request: cumulative exponential gaps over the
+    rate (all at 0 when rate is 0, a closed batch).  Non-decreasing."""
+    if not rate:
+        return [0.0] * len(stream)
+    return list(np.cumsum([r.arrival_gap for r in stream]) / rate)
+
+
+def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=0.7, warmup=16):
+    """Poisson stream of fragment solves through the request server.
+
+    Fragment size k ~ U{k_range} (embedded problem: 2k orbitals, 4k qubits),
+    D ~ U{bonds}, DMET chemical-potential shift on the fragment orbitals.  The
+    server's capacity is measured first on a closed batch of the same request
+    mix; arrivals then follow the stream's exponential gaps at load * capacity.
+    Latency is submit-to-result on the host clock (problem compile, queueing
+    and device time)."""
+    from workloads import serving_stream
+
+    reqs = serving_stream(n_req + warmup, seed=seed, k_range=k_range, bonds=bonds)
+    ctx = q2c.Context(0)
+
+    def run(stream, rate):
+        srv = q2c.Server(ctx, slots_per_class=64, gates_per_step=512)
+        pending = list(zip(arrival_times(stream, rate), stream))
+        res, t0, i = {}, time.perf_counter(), 0
+        while len(res) < len(stream):
+            now = time.perf_counter() - t0
+            while i < len(pending) and pending[i][0] <= now:
+                r = pending[i][1]
+                I = r.integrals()
+                srv.submit(r.index, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), r.max_bond,
+                           q2c.Q2C_FP64, r.n_frag_orb)
+                i += 1
+            srv.step()
+            for x in srv.poll():
+                res[x["tag"]] = x
+            time.sleep(0.0005)
+        srv.close()
+        return res, time.perf_counter() - t0
+
+    cap_res, cap_t = run(reqs[:warmup], 0.0)
+    capacity = len(cap_res) / cap_t
+    rate = load * capacity
+    res, wall = run(reqs, rate)
+    measured = [res[r.index] for r in reqs[warmup:]]
+    bad = [x for x in measured if x["status"] != 0]
+    lat = np.array([x["done_s"] - x["submit_s"] for x in measured])
+    span = max(x["done_s"] for x in measured) - min(x["submit_s"] for x in measured)
+    classes = {}
+    for r, x in zip(reqs[warmup:], measured):
+        key = f"{4 * r.n_frag_orb}q_D{r.max_bond}"
+        classes.setdefault(key, []).append(x["done_s"] - x["submit_s"])
+    ctx.close()
+    return {
+        "requests": len(measured), "errors": len(bad), "evals_per_s": len(measured) / span,
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "capacity_evals_per_s": capacity, "offered_load": load, "arrival_rate_per_s": rate,
+        "per_class": {k: {"n": len(v), "p50_s": float(np.percentile(v, 50)), "p99_s": float(np.percentile(v, 99))}
+                      for k, v in sorted(classes.items())},
+        "workload": (f"fragment solves: k ~ U{{{k_range[0]}..{k_range[1]}}} fragment orbitals embedded in 2k "
+                     f"orbitals ({4 * k_range[0]}-{4 * k_range[1]} qubits), D ~ U{list(bonds)}, FP64, "
+                     f"Poisson arrivals at {load} of the measured capacity, {warmup} warm-up requests excluded"),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +176,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256,
                     help="circuits in the batched measurement (0 to skip)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve", type=int, default=64, help="measured requests of the serving run (0 to skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -235,6 +302,11 @@ def main():
         }
         bprob.close()
         bctx.close()
+    if args.serve > 0:
+        log("serving stream ...")
+        out["serving"] = serve_bench(q2c, args.serve)
+        log(f"serving: {out['serving']['evals_per_s']:.2f} evals/s p50 {out['serving']['p50_s']:.2f}s "
+            f"p99 {out['serving']['p99_s']:.2f}s")
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(cfg, flops_eval, args.cpu_seconds)

@@ -1,0 +1,24 @@
+"""Host-side pieces of bench.py that need no GPU."""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import bench  # noqa: E402
+from workloads import serving_stream  # noqa: E402
+
+
+def test_arrival_times_are_cumulative_gaps():
+    s = serving_stream(20, seed=9, k_range=(1, 2), bonds=(4,))
+    t = bench.arrival_times(s, 2.0)
+    assert np.all(np.diff(t) >= 0)
+    assert np.allclose(t, np.cumsum([r.arrival_gap for r in s]) / 2.0)
+    assert bench.arrival_times(s, 0.0) == [0.0] * 20
+
+
+def test_gate_flops_formula():
+    # 128 x 128 saturated gate: contraction 32*64^3 + 128*64^2, SVD 4(4 m n^2 + 8 n^3), update 8*128*128*64
+    f = bench.gate_flops(64, 64, 64, 64)
+    assert f == 32 * 64 ** 3 + 128 * 64 ** 2 + 4 * (4 * 128 ** 3 + 8 * 128 ** 3) + 8 * 128 * 128 * 64
