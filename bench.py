@@ -35,6 +35,25 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one launch of the gate kernel at the default workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by what the same counters
+# read for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only
+# for the kernel source it was measured on (sha256 prefix); otherwise null.
+GATE_TRAFFIC = {"kernels_sha256": "d14ca005bfde3bdc", "workload": "q16_d64", "precision": "fp64",
+                "bytes_per_launch": (2.0 * 2062.5 + 1.0 * 1369811.0) * 1024.0}
+
+
+def measured_traffic(workload: str):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2207_03711_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != GATE_TRAFFIC["kernels_sha256"] or workload != GATE_TRAFFIC["workload"]:
+        return None
+    return GATE_TRAFFIC["bytes_per_launch"]
+
+
 WORKLOAD_TEXT = {
     "q8_d16": "8 qubits (4 orbitals, 4 electrons), D=16 (full), complex128, single energy evaluation",
     "q16_d64": "16 qubits (8 orbitals, 8 electrons), D=64, complex128, single energy evaluation",
@@ -177,7 +196,20 @@ def main():
                     help="circuits in the batched measurement (0 to skip)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve", type=int, default=64, help="measured requests of the serving run (0 to skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run three device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        n = args.calibrate_copy * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the energy path has no multi-GPU mode in this build "
@@ -258,7 +290,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload),
+            "traffic_unit": "B/launch",
             "flops_per_launch": flops_per_launch,
             "ms_per_launch": ms_per_launch,
             "launches_per_eval": launches / K,
