@@ -152,6 +152,20 @@ int mps_expect_pauli_batch(mps_state* s, int n_strings, int n_words,
                            const uint64_t* x_masks, const uint64_t* z_masks,
                            double* out_re, double* out_im);
 
+/* Host only (no device call): the order in which the transfer sweeps visit
+ * Pauli strings so that strings with a common leading part share its
+ * transfer steps (Sec. III-B, prefix sharing of the strings of Eq. 2).
+ * Strings are sorted by lowest non-identity qubit, then by their letters
+ * qubit by qubit upward, the identity first.
+ *   x_masks, z_masks  n_strings uint64 each (n_qubits <= 64).
+ *   order  out, n_strings: sorted position -> input index.
+ *   share  out, n_strings: transfer steps sorted string t has in common with
+ *          sorted string t-1 (0 for t = 0 or a different lowest qubit).
+ *   steps  nullable out, 2 int64: transfer steps without and with sharing
+ *          along the whole order (the second = nodes of the prefix trie). */
+int q2c_pauli_prefix_order(int n_strings, const uint64_t* x_masks, const uint64_t* z_masks,
+                           int* order, int* share, int64_t* steps);
+
 /* Copy the site tensors and Schmidt values to the host (debugging, checks).
  *   chi_out   n_qubits+1 ints: chi_out[0] = 1, chi_out[n+1] = right bond of
  *             site n, chi_out[N] = 1.

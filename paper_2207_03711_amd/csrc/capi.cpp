@@ -34,7 +34,7 @@ struct mps_state {
   q2c_ctx* ctx = nullptr;
   int n = 0, D = 0, precision = 0;
   std::unique_ptr<Batch> batch;
-  DBuf occ, gsite, grot, gmat, scratch, ev_re, ev_im, sx, sz;
+  DBuf occ, gsite, grot, gmat, scratch, ev_re, ev_im, sx, sz, sord, sshr;
   int scratch_wg = 0;
 };
 
@@ -42,7 +42,7 @@ struct vqe_problem {
   q2c_ctx* ctx = nullptr;
   q2c::Problem host;
   q2c::DevProblem dev;
-  DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, occ;
+  DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, sord, sshr, occ;
   std::map<std::tuple<int, int, int>, std::unique_ptr<Batch>> batches;  // (D, slots, precision)
   DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi;
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
@@ -117,12 +117,12 @@ void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int
   const int ns = p->dev.n_strings;
   ensure(ctx, p->ev_re, p->evr_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
   ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
-  int n_wg = std::max(1, std::min(ns, 1024 / std::max(1, n_slots)));
-  if (n_wg < 4) n_wg = std::min(ns, 4);
-  const size_t scr = size_t(n_slots) * n_wg * 3 * size_t(B.cm) * B.cm * sizeof(double2);
+  const int n_wg = pauli_workgroups(ns, n_slots);
+  const size_t scr =
+      size_t(n_slots) * n_wg * q2c::pauli_scratch_mats(H.n_qubits) * size_t(B.cm) * B.cm * sizeof(double2);
   ensure(ctx, p->scratch, p->scratch_cap, scr);
-  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->scratch.as<double2>(), n_wg, B.cm,
-                              p->ev_re.as<double>(), p->ev_im.as<double>(), st),
+  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
+                              p->scratch.as<double2>(), n_wg, B.cm, p->ev_re.as<double>(), p->ev_im.as<double>(), st),
             "pauli");
   hip_check(hipEventRecord(ev.e[3], st), "event");
   ensure(ctx, p->energies, p->en_cap, sizeof(double) * n_slots);
@@ -303,18 +303,40 @@ int mps_expect_pauli_batch(mps_state* s, int n_strings, int n_words, const uint6
     s->ev_im = DBuf(ctx, sizeof(double) * n_strings);
     hip_check(hipMemcpyAsync(s->sx.p, x_masks, sizeof(uint64_t) * n_strings, hipMemcpyHostToDevice, st), "copy");
     hip_check(hipMemcpyAsync(s->sz.p, z_masks, sizeof(uint64_t) * n_strings, hipMemcpyHostToDevice, st), "copy");
-    const int n_wg = std::min(n_strings, 256);
+    const q2c::PrefixOrder po = q2c::pauli_prefix_order(x_masks, z_masks, n_strings);
+    s->sord = DBuf(ctx, sizeof(int) * n_strings);
+    s->sshr = DBuf(ctx, sizeof(int) * n_strings);
+    hip_check(hipMemcpyAsync(s->sord.p, po.order.data(), sizeof(int) * n_strings, hipMemcpyHostToDevice, st), "copy");
+    hip_check(hipMemcpyAsync(s->sshr.p, po.share.data(), sizeof(int) * n_strings, hipMemcpyHostToDevice, st), "copy");
+    const int n_wg = pauli_workgroups(n_strings, 1);
     if (s->scratch_wg < n_wg) {
-      s->scratch = DBuf(ctx, size_t(n_wg) * 3 * B.cm * B.cm * sizeof(double2));
+      s->scratch = DBuf(ctx, size_t(n_wg) * q2c::pauli_scratch_mats(s->n) * B.cm * B.cm * sizeof(double2));
       s->scratch_wg = n_wg;
     }
     hip_check(q2c::launch_envs(B.d, st), "envs");
-    hip_check(q2c::launch_pauli(B.d, s->sx.as<uint64_t>(), s->sz.as<uint64_t>(), n_strings, s->scratch.as<double2>(),
-                                n_wg, B.cm, s->ev_re.as<double>(), s->ev_im.as<double>(), st),
+    hip_check(q2c::launch_pauli(B.d, s->sx.as<uint64_t>(), s->sz.as<uint64_t>(), n_strings, s->sord.as<int>(),
+                                s->sshr.as<int>(), s->scratch.as<double2>(), n_wg, B.cm, s->ev_re.as<double>(),
+                                s->ev_im.as<double>(), st),
               "pauli");
     hip_check(hipMemcpyAsync(out_re, s->ev_re.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
     if (out_im) hip_check(hipMemcpyAsync(out_im, s->ev_im.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
     hip_check(hipStreamSynchronize(st), "sync");
+  });
+}
+
+int q2c_pauli_prefix_order(int n_strings, const uint64_t* x_masks, const uint64_t* z_masks, int* order, int* share,
+                           int64_t* steps) {
+  return guarded([&] {
+    require(n_strings >= 0, "n_strings < 0");
+    if (n_strings == 0) return;
+    require(x_masks && z_masks && order && share, "NULL argument");
+    const q2c::PrefixOrder po = q2c::pauli_prefix_order(x_masks, z_masks, n_strings);
+    std::copy(po.order.begin(), po.order.end(), order);
+    std::copy(po.share.begin(), po.share.end(), share);
+    if (steps) {
+      steps[0] = po.steps_plain;
+      steps[1] = po.steps_shared;
+    }
   });
 }
 
@@ -424,6 +446,9 @@ int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1, co
       up(p->sx, sx.data(), sizeof(uint64_t) * sx.size());
       up(p->sz, sz.data(), sizeof(uint64_t) * sz.size());
       up(p->sc, sc.data(), sizeof(double) * sc.size());
+      const q2c::PrefixOrder po = q2c::pauli_prefix_order(sx.data(), sz.data(), d.n_strings);
+      up(p->sord, po.order.data(), sizeof(int) * po.order.size());
+      up(p->sshr, po.share.data(), sizeof(int) * po.share.size());
       up(p->occ, occ.data(), occ.size());
       d.gate_site = p->gsite.as<int>();
       d.gate_rot = p->grot.as<int>();
@@ -434,6 +459,8 @@ int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1, co
       d.str_x = p->sx.as<uint64_t>();
       d.str_z = p->sz.as<uint64_t>();
       d.str_c = p->sc.as<double>();
+      d.str_order = p->sord.as<int>();
+      d.str_share = p->sshr.as<int>();
       hip_check(hipStreamSynchronize(st), "sync");
     }
     *out = p.release();

@@ -303,4 +303,44 @@ Problem compile_problem(int n_orb, int n_elec, const double* h1, const double* e
   return P;
 }
 
+PrefixOrder pauli_prefix_order(const uint64_t* x, const uint64_t* z, int n) {
+  PrefixOrder po;
+  po.order.resize(n);
+  po.share.assign(n, 0);
+  auto lo_of = [&](int s) { return (x[s] | z[s]) ? __builtin_ctzll(x[s] | z[s]) : -1; };
+  auto len_of = [&](int s) {
+    const uint64_t m = x[s] | z[s];
+    return m ? 64 - __builtin_clzll(m) - __builtin_ctzll(m) : 0;
+  };
+  auto letter = [&](int s, int k) { return int((x[s] >> k) & 1) | int((z[s] >> k) & 1) << 1; };
+  for (int i = 0; i < n; ++i) po.order[i] = i;
+  std::stable_sort(po.order.begin(), po.order.end(), [&](int a, int b) {
+    const int la = lo_of(a), lb = lo_of(b);
+    if (la != lb) return la < lb;
+    if (la < 0) return false;
+    for (int k = la; k < 64; ++k) {
+      const int ca = letter(a, k), cb = letter(b, k);
+      if (ca != cb) return ca < cb;
+    }
+    return false;
+  });
+  for (int t = 0; t < n; ++t) {
+    const int s = po.order[t];
+    const int len = len_of(s);
+    po.steps_plain += len;
+    int sh = 0;
+    if (t > 0) {
+      const int p = po.order[t - 1];
+      const int lo = lo_of(s);
+      if (lo >= 0 && lo == lo_of(p)) {
+        const int cap = std::min(len, len_of(p));
+        while (sh < cap && letter(s, lo + sh) == letter(p, lo + sh)) ++sh;
+      }
+    }
+    po.share[t] = sh;
+    po.steps_shared += len - sh;
+  }
+  return po;
+}
+
 }  // namespace q2c

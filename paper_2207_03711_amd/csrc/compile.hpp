@@ -46,4 +46,18 @@ struct Problem {
 // Throws std::invalid_argument on bad input.
 Problem compile_problem(int n_orb, int n_elec, const double* h1, const double* eri, double e_const);
 
+// Prefix order of Pauli strings for the transfer sweeps: strings sorted by
+// their lowest non-identity site, then by their letters site by site upward
+// (the identity string first).  share[t] = number of leading transfer steps
+// (sites from that lowest site on) that sorted string t has in common with
+// sorted string t - 1; 0 for t = 0, for a different lowest site and for
+// either string being the identity.  Never more than the length of either.
+struct PrefixOrder {
+  std::vector<int> order;  // sorted position -> input index
+  std::vector<int> share;  // per sorted position
+  long steps_plain = 0;    // transfer steps without reuse
+  long steps_shared = 0;   // with reuse along the whole order
+};
+PrefixOrder pauli_prefix_order(const uint64_t* x, const uint64_t* z, int n);
+
 }  // namespace q2c

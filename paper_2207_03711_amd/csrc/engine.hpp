@@ -25,6 +25,8 @@ struct DevProblem {
   uint64_t* str_x = nullptr;    // [n_strings]
   uint64_t* str_z = nullptr;    // [n_strings]
   double* str_c = nullptr;      // [n_strings]
+  int* str_order = nullptr;     // [n_strings] prefix order of the strings (sorted position -> index)
+  int* str_share = nullptr;     // [n_strings] transfer steps shared with the previous sorted string
 };
 
 // A batch of MPS "slots" with a common shape (qubits, bond cap).  Every
@@ -98,9 +100,14 @@ hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d
 hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, const double2* d_pre,
                         const double2* d_post, int g0, int g1, int n_rot, SvdParams sp, hipStream_t st);
 hipError_t launch_envs(const DevBatch& b, hipStream_t st);
-// d_scratch: n_slots * n_wg * 3 * cm * cm double2, cm = largest bond cap.
+// d_order / d_share: prefix order (nullable: input order, no reuse).  Each
+// workgroup takes a contiguous run of ceil(n_strings / n_wg) sorted strings.
+// d_scratch: n_slots * n_wg * pauli_scratch_mats(N) * cm * cm double2,
+// cm = largest bond cap.
 hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings,
-                        double2* d_scratch, int n_wg, int cm, double* d_ev_re, double* d_ev_im, hipStream_t st);
+                        const int* d_order, const int* d_share, double2* d_scratch, int n_wg, int cm,
+                        double* d_ev_re, double* d_ev_im, hipStream_t st);
+inline int pauli_scratch_mats(int n_qubits) { return n_qubits + 2; }
 hipError_t launch_energy_reduce(const DevBatch& b, const double* d_coeff, const double* d_ev_re,
                                 const double* d_ev_im, int n_strings, double c_identity,
                                 double* d_energy, hipStream_t st);

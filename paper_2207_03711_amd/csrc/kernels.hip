@@ -1586,9 +1586,17 @@ __global__ __launch_bounds__(kBlock) void k_envs(DevBatch b) {
 
 // --------------------------------------------------------- Pauli sweeps ---
 
+// Transfer sweeps of the Pauli strings (Eq. 2 by exact contraction).  The
+// strings are visited in a prefix order (lowest non-identity site, then the
+// letters site by site): string t shares its first share[t] transfer steps
+// with string t - 1, so a workgroup walking a contiguous run of the order
+// keeps a stack of partial left transfers and recomputes only the rest (the
+// prefix trie of the strings, one node per transfer step).  Without order,
+// strings go in their own order with no reuse.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __restrict__ sx,
                                                   const uint64_t* __restrict__ sz, int n_strings,
+                                                  const int* __restrict__ order, const int* __restrict__ share,
                                                   double2* scratch, int cm, double* ev_re, double* ev_im) {
   __shared__ S lds_gemm[2 * 64 * 8];
   __shared__ double red[kBlock / 64];
@@ -1597,11 +1605,15 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
   SlotView v = slot_view(b, slot);
   const S* L = reinterpret_cast<const S*>(b.envL + slot * b.env_stride);
   const S* R = reinterpret_cast<const S*>(b.envR + slot * b.env_stride);
-  S* T0 = reinterpret_cast<S*>(scratch) + ((long)r * gridDim.x + blockIdx.x) * 3 * (long)cm * cm;
-  S* T1 = T0 + (long)cm * cm;
-  S* X = T1 + (long)cm * cm;
+  const long mat = (long)cm * cm;
+  // per workgroup: X, then the stack of transfers after 1 .. N sites
+  S* X = reinterpret_cast<S*>(scratch) + ((long)r * gridDim.x + blockIdx.x) * (N + 2) * mat;
+  S* stk = X + mat;  // transfer after d sites at stk + (d - 1) * mat
   const double nrm = double(L[b.env_off[N]].x);
-  for (int s = blockIdx.x; s < n_strings; s += gridDim.x) {
+  const int per = (n_strings + gridDim.x - 1) / gridDim.x;
+  const int t0 = blockIdx.x * per, t1 = min(n_strings, t0 + per);
+  for (int t = t0; t < t1; ++t) {
+    const int s = order ? order[t] : t;
     const uint64_t x = sx[s], z = sz[s];
     const uint64_t mk = x | z;
     double2 ev = cmk(0.0, 0.0);
@@ -1609,16 +1621,12 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
       ev = cmk(1.0, 0.0);
     } else {
       const int lo = __builtin_ctzll(mk), hi = 63 - __builtin_clzll(mk);
-      const int c0 = v.chi[lo];
-      const S* Llo = L + b.env_off[lo];
-      for (int idx = threadIdx.x; idx < c0 * c0; idx += blockDim.x) {
-        const int a = idx / c0, c = idx - a * c0;
-        T0[(long)a * cm + c] = Llo[(long)a * b.cap[lo] + c];
-      }
-      __syncthreads();
-      S* T = T0;
-      S* Tn = T1;
-      for (int k = lo; k <= hi; ++k) {
+      const int d0 = (t == t0 || !share) ? 0 : share[t];
+      for (int d = d0; d <= hi - lo; ++d) {
+        const int k = lo + d;
+        const S* T = d == 0 ? L + b.env_off[lo] : stk + (long)(d - 1) * mat;
+        const int ldt = d == 0 ? b.cap[lo] : cm;
+        S* Tn = stk + (long)d * mat;
         const int cl = v.chi[k], cr = v.chi[k + 1];
         const int capr = b.cap[k + 1];
         const S* Bk = reinterpret_cast<const S*>(v.sites) + b.site_off[k];
@@ -1628,14 +1636,13 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
           S ph = cval<S>(1.0, 0.0);
           if (zb && !xb) ph = cval<S>(i == 0 ? 1.0 : -1.0, 0.0);  // Z
           if (zb && xb) ph = cval<S>(0.0, i == 0 ? -1.0 : 1.0);   // Y: <0|Y|1> = -i
-          bgemm<false, false, S>(cl, cr, cl, T, cm, Bk + ip * capr, 2 * capr, X, cm, cval<S>(1.0, 0.0), false, lds_gemm);
+          bgemm<false, false, S>(cl, cr, cl, T, ldt, Bk + ip * capr, 2 * capr, X, cm, cval<S>(1.0, 0.0), false,
+                                 lds_gemm);
           bgemm<true, false, S>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1, lds_gemm);
         }
-        S* t = T;
-        T = Tn;
-        Tn = t;
       }
       // <P> = sum_{c,c'} T[c][c'] R[c][c'],  R[c][c'] = Rt[c'][c]
+      const S* T = stk + (long)(hi - lo) * mat;
       const int ch = v.chi[hi + 1];
       const S* Rh = R + b.env_off[hi + 1];
       const int ldr = b.cap[hi + 1];
@@ -1729,15 +1736,16 @@ hipError_t launch_envs(const DevBatch& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings, double2* d_scratch,
-                        int n_wg, int cm, double* d_ev_re, double* d_ev_im, hipStream_t st) {
+hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings, const int* d_order,
+                        const int* d_share, double2* d_scratch, int n_wg, int cm, double* d_ev_re, double* d_ev_im,
+                        hipStream_t st) {
   if (n_strings == 0) return hipSuccess;
   if (b.mixed)
-    hipLaunchKernelGGL(k_pauli<float2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch,
-                       cm, d_ev_re, d_ev_im);
+    hipLaunchKernelGGL(k_pauli<float2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
+                       d_share, d_scratch, cm, d_ev_re, d_ev_im);
   else
-    hipLaunchKernelGGL(k_pauli<double2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_scratch,
-                       cm, d_ev_re, d_ev_im);
+    hipLaunchKernelGGL(k_pauli<double2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
+                       d_share, d_scratch, cm, d_ev_re, d_ev_im);
   return hipGetLastError();
 }
 

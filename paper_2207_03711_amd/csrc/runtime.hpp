@@ -280,4 +280,14 @@ inline void check_flags(const std::vector<int>& flags) {
 
 constexpr int kGateChunk = 8192;  // gates per launch of the gate kernel
 
+// Workgroups per slot of the Pauli sweep: about 1024 workgroups in all to
+// fill the chip, but runs of at least kPauliRun sorted strings each, so that
+// a workgroup reuses the shared prefixes of its run.
+constexpr int kPauliRun = 32;
+inline int pauli_workgroups(int n_strings, int n_slots) {
+  int n_wg = std::max(1, 1024 / std::max(1, n_slots));
+  n_wg = std::min(n_wg, (n_strings + kPauliRun - 1) / kPauliRun);
+  return std::max(1, std::min(n_wg, n_strings));
+}
+
 }  // namespace

@@ -21,6 +21,7 @@ struct SrvRequest {
   std::vector<double> theta;
   double t_submit = 0.0, t_admit = -1.0;
   DBuf sx, sz, sc;    // Hamiltonian strings, then 2 n_frag_orb single-Z strings (coefficient 0)
+  DBuf sord, sshr;    // their prefix order
   int n_str = 0;
 };
 
@@ -134,7 +135,7 @@ std::unique_ptr<SrvClass> make_class(q2c_server* s, const SrvRequest& r) {
   c->phi = DBuf(ctx, sizeof(double) * std::max(1, S * d.n_rot));
   c->energy = DBuf(ctx, sizeof(double));
   const int cm = c->batch->cm;
-  c->scratch = DBuf(ctx, size_t(c->n_wg) * 3 * cm * cm * sizeof(double2));
+  c->scratch = DBuf(ctx, size_t(c->n_wg) * q2c::pauli_scratch_mats(c->n_qubits) * cm * cm * sizeof(double2));
   c->batch->d.phi = c->phi.as<double>();
   c->batch->d.cursor = c->cursor.as<int>();
   c->batch->d.n_gates = d.n_gates;
@@ -172,6 +173,9 @@ void admit(q2c_server* s, SrvClass& c, int slot, std::unique_ptr<SrvRequest> r) 
   upload(ctx, r->sx, sx, st);
   upload(ctx, r->sz, sz, st);
   upload(ctx, r->sc, sc, st);
+  const q2c::PrefixOrder po = q2c::pauli_prefix_order(sx.data(), sz.data(), r->n_str);
+  upload(ctx, r->sord, po.order, st);
+  upload(ctx, r->sshr, po.share, st);
   if (!r->theta.empty())
     hip_check(hipMemcpyAsync(c.theta1.p, r->theta.data(), sizeof(double) * r->theta.size(), hipMemcpyHostToDevice, st),
               "copy theta");
@@ -207,9 +211,10 @@ void finish(q2c_server* s, SrvClass& c, int slot) {
   res.submit_s = r.t_submit;
   res.admit_s = r.t_admit;
   hip_check(q2c::launch_envs(b, st), "envs");
-  const int n_wg = std::max(1, std::min(ns, c.n_wg));
-  hip_check(q2c::launch_pauli(b, r.sx.as<uint64_t>(), r.sz.as<uint64_t>(), ns, c.scratch.as<double2>(), n_wg,
-                              c.batch->cm, c.ev_re.as<double>(), c.ev_im.as<double>(), st),
+  const int n_wg = std::min(c.n_wg, pauli_workgroups(ns, 1));
+  hip_check(q2c::launch_pauli(b, r.sx.as<uint64_t>(), r.sz.as<uint64_t>(), ns, r.sord.as<int>(), r.sshr.as<int>(),
+                              c.scratch.as<double2>(), n_wg, c.batch->cm, c.ev_re.as<double>(), c.ev_im.as<double>(),
+                              st),
             "pauli");
   hip_check(q2c::launch_energy_reduce(b, r.sc.as<double>(), c.ev_re.as<double>(), c.ev_im.as<double>(), ns,
                                       r.prob.c_identity, c.energy.as<double>(), st),

@@ -130,6 +130,7 @@ SIGNATURES = {
     "mps_destroy": (C.c_int, [_vp]),
     "mps_apply_gate": (C.c_int, [_vp, C.c_int, _pd, _pd]),
     "mps_expect_pauli_batch": (C.c_int, [_vp, C.c_int, C.c_int, _pu64, _pu64, _pd, _pd]),
+    "q2c_pauli_prefix_order": (C.c_int, [C.c_int, _pu64, _pu64, _pi, _pi, C.POINTER(C.c_int64)]),
     "mps_export": (C.c_int, [_vp, _pi, _pd, _pd]),
     "mps_get_stats": (C.c_int, [_vp, C.POINTER(q2c_stats)]),
     "vqe_problem_create": (C.c_int, [_vp, C.c_int, C.c_int, _pd, _pd, C.c_double, _pvp]),
@@ -220,6 +221,20 @@ def mps_expect_pauli_batch(s, x_masks, z_masks, n_qubits: int):
     nw = (n_qubits + 63) // 64
     _check(lib.mps_expect_pauli_batch(s, n, nw, x.ctypes.data_as(_pu64), z.ctypes.data_as(_pu64), _dp(re), _dp(im)))
     return re, im
+
+
+def pauli_prefix_order(x_masks, z_masks):
+    """Prefix order of Pauli strings: (order, share, (steps_plain, steps_shared))."""
+    x = np.ascontiguousarray(x_masks, dtype=np.uint64)
+    z = np.ascontiguousarray(z_masks, dtype=np.uint64)
+    n = len(x)
+    order = np.zeros(n, dtype=np.int32)
+    share = np.zeros(n, dtype=np.int32)
+    steps = np.zeros(2, dtype=np.int64)
+    _check(lib.q2c_pauli_prefix_order(n, x.ctypes.data_as(_pu64), z.ctypes.data_as(_pu64),
+                                      order.ctypes.data_as(_pi), share.ctypes.data_as(_pi),
+                                      steps.ctypes.data_as(C.POINTER(C.c_int64))))
+    return order, share, (int(steps[0]), int(steps[1]))
 
 
 def mps_export(s, n_qubits: int):

@@ -135,3 +135,71 @@ def test_context_without_gpu_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     _expect_error(lambda: q2c.q2c_ctx_create(0), q2c.Q2C_ERR_DEVICE)
+
+
+def _letters(x, z, lo, hi):
+    return tuple(((x >> k) & 1) | (((z >> k) & 1) << 1) for k in range(lo, hi + 1))
+
+
+def _support(x, z):
+    m = x | z
+    if m == 0:
+        return None
+    return (m & -m).bit_length() - 1, m.bit_length() - 1
+
+
+@pytest.mark.parametrize("which", ["q8", "q16", "random"])
+def test_pauli_prefix_order(which):
+    """The prefix order is a permutation sorted by (lowest qubit, letters);
+    each share is the common leading run with the previous sorted string;
+    and the transfer steps it leaves equal the node count of the prefix
+    trie, counted here from the set of distinct (lowest qubit, prefix)."""
+    if which == "random":
+        rng = np.random.default_rng(11)
+        n = 300
+        x = rng.integers(0, 1 << 12, n, dtype=np.uint64) & rng.integers(0, 1 << 12, n, dtype=np.uint64)
+        z = rng.integers(0, 1 << 12, n, dtype=np.uint64) & rng.integers(0, 1 << 12, n, dtype=np.uint64)
+        x[:3] = 0
+        z[:3] = 0  # identity strings, repeated
+        x[3:6] = x[6]
+        z[3:6] = z[6]  # repeated strings
+    else:
+        I = CONFIGS["q8_d16" if which == "q8" else "q16_d64"].integrals()
+        _, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri, I.e_const))
+        x = np.array([t[0] for t in terms], dtype=np.uint64)
+        z = np.array([t[1] for t in terms], dtype=np.uint64)
+    order, share, (plain, shared) = q2c.pauli_prefix_order(x, z)
+    n = len(x)
+    assert sorted(order.tolist()) == list(range(n))
+    xs = [int(v) for v in x]
+    zs = [int(v) for v in z]
+
+    def key(s):
+        sp = _support(xs[s], zs[s])
+        return (-1, ()) if sp is None else (sp[0], _letters(xs[s], zs[s], sp[0], 63))
+
+    keys = [key(int(s)) for s in order]
+    assert keys == sorted(keys)
+    nodes, total = set(), 0
+    for t, s in enumerate(order):
+        s = int(s)
+        sp = _support(xs[s], zs[s])
+        want = 0
+        if sp is not None:
+            lo, hi = sp
+            L = _letters(xs[s], zs[s], lo, hi)
+            total += len(L)
+            for d in range(1, len(L) + 1):
+                nodes.add((lo, L[:d]))
+            if t > 0:
+                p = int(order[t - 1])
+                spp = _support(xs[p], zs[p])
+                if spp is not None and spp[0] == lo:
+                    Lp = _letters(xs[p], zs[p], lo, spp[1])
+                    while want < min(len(L), len(Lp)) and L[want] == Lp[want]:
+                        want += 1
+        assert share[t] == want, (t, s)
+    assert plain == total
+    assert shared == len(nodes)
+    if which == "q16":
+        assert shared < plain / 3.5
