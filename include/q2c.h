@@ -75,6 +75,10 @@ typedef struct {
                                singular values, twisted-factorisation vectors (D <= 64;
                                falls back to 1 when the vectors cannot be certified);
                                1: LQ+QR-preconditioned one-sided Jacobi                    */
+  int shift_from_start;     /* parameter-shift circuits: 0 -> each shifted circuit starts
+                               from a copy of the unshifted circuit's state at its first
+                               angle-dependent gate (same energies, about half the gates);
+                               1 -> every circuit runs from the first gate                 */
 } q2c_opts;
 
 /* Statistics of the last state evolution (all over the gates applied). */
@@ -221,7 +225,11 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
 
 /* Gradient by the two-term parameter shift of every rotation angle:
  * dE/dtheta_k = sum_{m in k} (-2 c_m) (E(phi_m + pi/2) - E(phi_m - pi/2)) / 2.
- * All shifted circuits (2 per rotation) and the unshifted one run as a batch.
+ * All shifted circuits (2 per rotation) and the unshifted one run as
+ * batches of concurrent circuits; by default (q2c_opts.shift_from_start = 0)
+ * the shifted circuits of a rotation start from the unshifted circuit's
+ * state at that rotation's first angle-dependent gate, which leaves every
+ * energy unchanged.  stats->gate_flops then counts every gate that ran once.
  *   grad    n_theta doubles.
  *   energy  nullable; E(theta). */
 int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int max_bond,

@@ -44,9 +44,10 @@ struct vqe_problem {
   q2c::DevProblem dev;
   DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, sord, sshr, occ;
   std::map<std::tuple<int, int, int>, std::unique_ptr<Batch>> batches;  // (D, slots, precision)
-  DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi;
+  DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi, cursor, pairs;
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
-         phi_cap = 0;
+         phi_cap = 0, cursor_cap = 0, pairs_cap = 0;
+  std::vector<int> fork_gate;  // per rotation: its first gate whose matrix depends on the rotation's angle
 };
 
 namespace {
@@ -57,6 +58,90 @@ void ensure(q2c_ctx* ctx, DBuf& buf, size_t& cap, size_t bytes) {
   cap = bytes;
 }
 
+Batch& batch_for(vqe_problem* p, int D, int n_slots, int precision) {
+  auto key = std::make_tuple(D, n_slots, precision);
+  if (!p->batches.count(key))
+    p->batches[key] = std::make_unique<Batch>(p->ctx, p->host.n_qubits, D, n_slots, precision);
+  return *p->batches[key];
+}
+
+bool progress_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("Q2C_PROGRESS");
+    return e && *e && *e != '0';
+  }();
+  return on;
+}
+
+// Gates [g0, g1) of every slot of db, in launches of up to kGateChunk gates.
+// With db.cursor set, each launch instead runs up to kGateChunk gates of each
+// slot from its cursor, and the launches cover g1 - g0 gates per slot.
+int run_gates(vqe_problem* p, const q2c::DevBatch& db, int g0, int g1, hipStream_t st) {
+  const q2c::SvdParams sp = svd_params(p->ctx);
+  const auto tp0 = std::chrono::steady_clock::now();
+  int launches = 0;
+  for (int c0 = g0; c0 < g1; c0 += kGateChunk) {
+    const int c1 = std::min(g1, c0 + kGateChunk);
+    hip_check(q2c::launch_gates(db, p->dev.gate_site, p->dev.gate_rot, p->dev.gate_pre, p->dev.gate_post,
+                                db.cursor ? 0 : c0, db.cursor ? c1 - c0 : c1, p->dev.n_rot, sp, st),
+              "gates");
+    ++launches;
+    if (progress_enabled()) {
+      hip_check(hipStreamSynchronize(st), "sync");
+      std::fprintf(stderr, "[q2c] %d circuit(s): gates %d/%d done, %.1f s\n", db.n_slots, c1, g1,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - tp0).count());
+      std::fflush(stderr);
+    }
+  }
+  return launches;
+}
+
+// Energies of slots 0 .. n_slots-1 of db, whose gates have all run:
+// environments, Pauli sweeps, reduction; reads back energies, flags and
+// statistics and synchronises the stream.
+void finish_circuits(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, int n_slots, double* energies,
+                     std::vector<double>& stats_out, PhaseTimes& pt) {
+  Events ev;
+  q2c_ctx* ctx = p->ctx;
+  hipStream_t st = ctx->stream;
+  const auto& H = p->host;
+  hip_check(hipEventRecord(ev.e[0], st), "event");
+  hip_check(q2c::launch_envs(db, st), "envs");
+  hip_check(hipEventRecord(ev.e[1], st), "event");
+  const int ns = p->dev.n_strings;
+  ensure(ctx, p->ev_re, p->evr_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
+  ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
+  const int n_wg = pauli_workgroups(ns, n_slots);
+  const size_t scr =
+      size_t(n_slots) * n_wg * q2c::pauli_scratch_mats(H.n_qubits) * size_t(B.cm) * B.cm * sizeof(double2);
+  ensure(ctx, p->scratch, p->scratch_cap, scr);
+  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
+                              p->scratch.as<double2>(), n_wg, B.cm, p->ev_re.as<double>(), p->ev_im.as<double>(), st),
+            "pauli");
+  hip_check(hipEventRecord(ev.e[2], st), "event");
+  ensure(ctx, p->energies, p->en_cap, sizeof(double) * n_slots);
+  hip_check(q2c::launch_energy_reduce(db, p->dev.str_c, p->ev_re.as<double>(), p->ev_im.as<double>(), ns,
+                                      H.c_identity, p->energies.as<double>(), st),
+            "reduce");
+  hip_check(hipEventRecord(ev.e[3], st), "event");
+  std::vector<int> flags(n_slots);
+  stats_out.assign(size_t(n_slots) * q2c::kNStats, 0.0);
+  hip_check(hipMemcpyAsync(energies, p->energies.p, sizeof(double) * n_slots, hipMemcpyDeviceToHost, st), "copy E");
+  hip_check(hipMemcpyAsync(flags.data(), db.flags + db.slot0, sizeof(int) * n_slots, hipMemcpyDeviceToHost, st),
+            "copy flags");
+  hip_check(hipMemcpyAsync(stats_out.data(), db.stats + size_t(db.slot0) * q2c::kNStats,
+                           sizeof(double) * n_slots * q2c::kNStats, hipMemcpyDeviceToHost, st),
+            "copy stats");
+  hip_check(hipStreamSynchronize(st), "sync");
+  pt.env_ms += ev.ms(0, 1);
+  pt.pauli_ms += ev.ms(1, 2);
+  pt.reduce_ms += ev.ms(2, 3);
+  pt.circuits += n_slots;
+  check_flags(flags);
+  for (int i = 0; i < n_slots; ++i)
+    if (!std::isfinite(energies[i])) throw StatusError(Q2C_ERR_NUMERIC, "non-finite energy");
+}
+
 // Runs n_slots circuits of problem p with theta (n_slots x n_params) and
 // optional per-slot shifts; writes per-slot energies.
 void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int n_slots, const int* shift_rot,
@@ -65,11 +150,8 @@ void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int
   q2c_ctx* ctx = p->ctx;
   ctx->activate();
   hipStream_t st = ctx->stream;
-  const auto& H = p->host;
-  const int np = H.n_params;
-  auto key = std::make_tuple(D, n_slots, precision);
-  if (!p->batches.count(key)) p->batches[key] = std::make_unique<Batch>(ctx, H.n_qubits, D, n_slots, precision);
-  Batch& B = *p->batches[key];
+  const int np = p->host.n_params;
+  Batch& B = batch_for(p, D, n_slots, precision);
   q2c::DevBatch db = B.d;
 
   ensure(ctx, p->theta, p->theta_cap, sizeof(double) * std::max(1, n_slots * np));
@@ -90,62 +172,11 @@ void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int
 
   hip_check(q2c::launch_init_product(db, p->occ.as<uint8_t>(), st), "init");
   hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, d_shift_rot, d_shift_val, st), "angles");
-  const q2c::SvdParams sp = svd_params(ctx);
-  int launches = 0;
-  static const bool progress = [] {
-    const char* e = std::getenv("Q2C_PROGRESS");
-    return e && *e && *e != '0';
-  }();
-  const auto tp0 = std::chrono::steady_clock::now();
   hip_check(hipEventRecord(ev.e[0], st), "event");
-  for (int g0 = 0; g0 < p->dev.n_gates; g0 += kGateChunk) {
-    const int g1 = std::min(p->dev.n_gates, g0 + kGateChunk);
-    hip_check(q2c::launch_gates(db, p->dev.gate_site, p->dev.gate_rot, p->dev.gate_pre, p->dev.gate_post, g0, g1,
-                                p->dev.n_rot, sp, st),
-              "gates");
-    ++launches;
-    if (progress) {
-      hip_check(hipStreamSynchronize(st), "sync");
-      std::fprintf(stderr, "[q2c] %d circuit(s): gates %d/%d done, %.1f s\n", n_slots, g1, p->dev.n_gates,
-                   std::chrono::duration<double>(std::chrono::steady_clock::now() - tp0).count());
-      std::fflush(stderr);
-    }
-  }
+  pt.gate_launches += run_gates(p, db, 0, p->dev.n_gates, st);
   hip_check(hipEventRecord(ev.e[1], st), "event");
-  hip_check(q2c::launch_envs(db, st), "envs");
-  hip_check(hipEventRecord(ev.e[2], st), "event");
-  const int ns = p->dev.n_strings;
-  ensure(ctx, p->ev_re, p->evr_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
-  ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
-  const int n_wg = pauli_workgroups(ns, n_slots);
-  const size_t scr =
-      size_t(n_slots) * n_wg * q2c::pauli_scratch_mats(H.n_qubits) * size_t(B.cm) * B.cm * sizeof(double2);
-  ensure(ctx, p->scratch, p->scratch_cap, scr);
-  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
-                              p->scratch.as<double2>(), n_wg, B.cm, p->ev_re.as<double>(), p->ev_im.as<double>(), st),
-            "pauli");
-  hip_check(hipEventRecord(ev.e[3], st), "event");
-  ensure(ctx, p->energies, p->en_cap, sizeof(double) * n_slots);
-  hip_check(q2c::launch_energy_reduce(db, p->dev.str_c, p->ev_re.as<double>(), p->ev_im.as<double>(), ns,
-                                      H.c_identity, p->energies.as<double>(), st),
-            "reduce");
-  hip_check(hipEventRecord(ev.e[4], st), "event");
-  std::vector<int> flags(n_slots);
-  stats_out.assign(size_t(n_slots) * q2c::kNStats, 0.0);
-  hip_check(hipMemcpyAsync(energies, p->energies.p, sizeof(double) * n_slots, hipMemcpyDeviceToHost, st), "copy E");
-  hip_check(hipMemcpyAsync(flags.data(), db.flags, sizeof(int) * n_slots, hipMemcpyDeviceToHost, st), "copy flags");
-  hip_check(hipMemcpyAsync(stats_out.data(), db.stats, sizeof(double) * n_slots * q2c::kNStats, hipMemcpyDeviceToHost, st),
-            "copy stats");
-  hip_check(hipStreamSynchronize(st), "sync");
+  finish_circuits(p, B, db, n_slots, energies, stats_out, pt);
   pt.gate_ms += ev.ms(0, 1);
-  pt.env_ms += ev.ms(1, 2);
-  pt.pauli_ms += ev.ms(2, 3);
-  pt.reduce_ms += ev.ms(3, 4);
-  pt.gate_launches += launches;
-  pt.circuits += n_slots;
-  check_flags(flags);
-  for (int i = 0; i < n_slots; ++i)
-    if (!std::isfinite(energies[i])) throw StatusError(Q2C_ERR_NUMERIC, "non-finite energy");
 }
 
 void check_theta(const vqe_problem* p, const double* theta, int n_theta, int count) {
@@ -200,6 +231,7 @@ int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx**
     if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = size_t(64) << 30;
     require(o.sv_cutoff_rel < 1.0 && o.svd_tol < 1e-3, "bad tolerances");
     require(o.svd_algorithm == 0 || o.svd_algorithm == 1, "svd_algorithm must be 0 or 1");
+    require(o.shift_from_start == 0 || o.shift_from_start == 1, "shift_from_start must be 0 or 1");
     c->opts = o;
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
@@ -460,6 +492,13 @@ int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1, co
       d.str_z = p->sz.as<uint64_t>();
       d.str_c = p->sc.as<double>();
       d.str_order = p->sord.as<int>();
+      p->fork_gate.assign(H.rotations.size(), -1);
+      for (size_t g = 0; g < H.gates.size(); ++g) {
+        const int r = H.gates[g].rot;
+        if (r >= 0 && p->fork_gate[r] < 0) p->fork_gate[r] = int(g);
+      }
+      for (int f : p->fork_gate)
+        if (f < 0) throw std::logic_error("rotation without an angle-dependent gate");
       d.str_share = p->sshr.as<int>();
       hip_check(hipStreamSynchronize(st), "sync");
     }
@@ -577,10 +616,12 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
 }
 
 namespace {
-void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond, int precision,
-                    std::vector<double>& ep, std::vector<double>& em, double* base, std::vector<double>& all_st,
-                    PhaseTimes& pt) {
-  // circuits: (rot, +pi/2), (rot, -pi/2) for each listed rotation, then the base circuit if requested
+// Shifted-circuit energies, each circuit run from the start: (rot, +pi/2) and
+// (rot, -pi/2) for each listed rotation, then the unshifted circuit if
+// requested, in batches of the context's slot count.
+void shift_energies_from_start(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+                               int precision, std::vector<double>& en, bool want_base, std::vector<double>& all_st,
+                               PhaseTimes& pt) {
   const int np = p->host.n_params;
   std::vector<int> srot;
   std::vector<double> sval;
@@ -590,12 +631,13 @@ void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>&
     srot.push_back(m);
     sval.push_back(-0.5 * M_PI);
   }
-  if (base) {
+  if (want_base) {
     srot.push_back(-1);
     sval.push_back(0.0);
   }
   const int total = int(srot.size());
-  std::vector<double> en(total), st;
+  en.assign(total, 0.0);
+  std::vector<double> st;
   const int chunk = chunk_slots(p);
   std::vector<double> th(size_t(chunk) * np);
   for (int b0 = 0; b0 < total; b0 += chunk) {
@@ -604,13 +646,132 @@ void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>&
     run_circuits(p, max_bond, precision, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st, pt);
     all_st.insert(all_st.end(), st.begin(), st.end());
   }
-  ep.resize(rots.size());
-  em.resize(rots.size());
-  for (size_t i = 0; i < rots.size(); ++i) {
+}
+
+// The same energies with the shared prefixes run once.  The shifted circuits
+// of rotation m agree with the unshifted one up to the first gate that
+// depends on phi_m, its fork gate.  One base slot runs the unshifted circuit
+// and its state is copied at the fork gate of each listed rotation; the two
+// shifted circuits of m start from that copy at their fork gate.  Rotations
+// are taken in fork order, slots/2 at a time, so the circuits of one batch
+// have about the same number of gates left; every gate runs as in a run from
+// the start, so the energies are the same bit for bit.
+void shift_energies_forked(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+                           int precision, std::vector<double>& en, bool want_base, std::vector<double>& all_st,
+                           PhaseTimes& pt) {
+  q2c_ctx* ctx = p->ctx;
+  ctx->activate();
+  hipStream_t st = ctx->stream;
+  const auto& H = p->host;
+  const int np = H.n_params, n_gates = p->dev.n_gates;
+  const int nr = int(rots.size());
+  en.assign(2 * nr + (want_base ? 1 : 0), 0.0);
+  std::vector<int> ord(nr);
+  for (int i = 0; i < nr; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return p->fork_gate[rots[a]] < p->fork_gate[rots[b]]; });
+  const int W = std::max(1, chunk_slots(p) / 2);
+
+  // base slot: the unshifted circuit
+  Batch& base = batch_for(p, max_bond, 1, precision);
+  SlotStore snaps(ctx, base.d, std::min(W, std::max(1, nr)));
+  ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, 2 * W) * np));
+  ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(2 * W) * std::max(1, p->dev.n_rot));
+  DBuf base_phi(ctx, sizeof(double) * std::max(1, p->dev.n_rot));
+  q2c::DevBatch bd = base.d;
+  bd.phi = base_phi.as<double>();
+  if (np) hip_check(hipMemcpyAsync(p->theta.p, theta, sizeof(double) * np, hipMemcpyHostToDevice, st), "copy theta");
+  hip_check(q2c::launch_init_product(bd, p->occ.as<uint8_t>(), st), "init");
+  hip_check(q2c::launch_angles(bd, p->dev, p->theta.as<double>(), np, nullptr, nullptr, st), "angles");
+  int cur = 0;
+  Events ev;
+  std::vector<double> st_batch, e_batch;
+  for (int w0 = 0; w0 < nr; w0 += W) {
+    const int nw = std::min(W, nr - w0), nb = 2 * nw;
+    // the base slot advances to each fork gate of the window and is copied there
+    hip_check(hipEventRecord(ev.e[0], st), "event");
+    for (int i = 0; i < nw; ++i) {
+      const int f = p->fork_gate[rots[ord[w0 + i]]];
+      pt.gate_launches += run_gates(p, bd, cur, f, st);
+      cur = std::max(cur, f);
+      hip_check(q2c::launch_copy_slots(bd, snaps.d, nullptr, 1, make_int2(0, i), false, st), "snapshot");
+    }
+    // the window's shifted circuits, each from its copy and fork gate
+    Batch& B = batch_for(p, max_bond, nb, precision);
+    q2c::DevBatch db = B.d;
+    std::vector<double> th(size_t(nb) * np), sval(nb);
+    std::vector<int> srot(nb), cursor(nb);
+    std::vector<int2> pairs(nb);
+    for (int j = 0; j < nb; ++j) {
+      const int m = rots[ord[w0 + j / 2]];
+      std::copy(theta, theta + np, th.begin() + size_t(j) * np);
+      srot[j] = m;
+      sval[j] = (j % 2 == 0 ? 0.5 : -0.5) * M_PI;
+      cursor[j] = p->fork_gate[m];
+      pairs[j] = make_int2(j / 2, j);
+    }
+    ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * nb);
+    ensure(ctx, p->shift_val, p->sval_cap, sizeof(double) * nb);
+    ensure(ctx, p->cursor, p->cursor_cap, sizeof(int) * nb);
+    ensure(ctx, p->pairs, p->pairs_cap, sizeof(int2) * nb);
+    if (np) hip_check(hipMemcpyAsync(p->theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st), "copy theta");
+    hip_check(hipMemcpyAsync(p->shift_rot.p, srot.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy shifts");
+    hip_check(hipMemcpyAsync(p->shift_val.p, sval.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st), "copy shifts");
+    hip_check(hipMemcpyAsync(p->cursor.p, cursor.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy cursor");
+    hip_check(hipMemcpyAsync(p->pairs.p, pairs.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, st), "copy pairs");
+    db.phi = p->phi.as<double>();
+    hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, p->shift_rot.as<int>(),
+                                 p->shift_val.as<double>(), st),
+              "angles");
+    hip_check(q2c::launch_copy_slots(snaps.d, db, p->pairs.as<int2>(), nb, make_int2(0, 0), true, st), "restore");
+    db.cursor = p->cursor.as<int>();
+    db.n_gates = n_gates;
+    const int left = n_gates - p->fork_gate[rots[ord[w0]]];
+    pt.gate_launches += run_gates(p, db, 0, left, st);
+    hip_check(hipEventRecord(ev.e[1], st), "event");
+    e_batch.resize(nb);
+    finish_circuits(p, B, db, nb, e_batch.data(), st_batch, pt);
+    pt.gate_ms += ev.ms(0, 1);
+    for (int j = 0; j < nb; ++j) en[2 * ord[w0 + j / 2] + (j % 2)] = e_batch[j];
+    all_st.insert(all_st.end(), st_batch.begin(), st_batch.end());
+  }
+  // the base slot's own energy, or only its statistics (its gates count once)
+  std::vector<double> st_base(q2c::kNStats);
+  if (want_base) {
+    hip_check(hipEventRecord(ev.e[0], st), "event");
+    pt.gate_launches += run_gates(p, bd, cur, n_gates, st);
+    hip_check(hipEventRecord(ev.e[1], st), "event");
+    finish_circuits(p, base, bd, 1, &en[2 * nr], st_base, pt);
+    pt.gate_ms += ev.ms(0, 1);
+  } else {
+    std::vector<int> flag(1);
+    hip_check(hipMemcpyAsync(st_base.data(), bd.stats, sizeof(double) * q2c::kNStats, hipMemcpyDeviceToHost, st),
+              "copy stats");
+    hip_check(hipMemcpyAsync(flag.data(), bd.flags, sizeof(int), hipMemcpyDeviceToHost, st), "copy flags");
+    hip_check(hipStreamSynchronize(st), "sync");
+    check_flags(flag);
+    // physics statistics of a circuit that was not evaluated are not reported
+    for (int k : {q2c::kStatNorm, q2c::kStatMaxImag}) st_base[k] = 0.0;
+  }
+  all_st.insert(all_st.end(), st_base.begin(), st_base.end());
+}
+
+void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond, int precision,
+                    std::vector<double>& ep, std::vector<double>& em, double* base, std::vector<double>& all_st,
+                    PhaseTimes& pt) {
+  std::vector<double> en;
+  if (p->ctx->opts.shift_from_start)
+    shift_energies_from_start(p, theta, rots, max_bond, precision, en, base != nullptr, all_st, pt);
+  else
+    shift_energies_forked(p, theta, rots, max_bond, precision, en, base != nullptr, all_st, pt);
+  const size_t nr = rots.size();
+  ep.resize(nr);
+  em.resize(nr);
+  for (size_t i = 0; i < nr; ++i) {
     ep[i] = en[2 * i];
     em[i] = en[2 * i + 1];
   }
-  if (base) *base = en[total - 1];
+  if (base) *base = en[2 * nr];
 }
 }  // namespace
 

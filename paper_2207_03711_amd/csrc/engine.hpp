@@ -95,6 +95,10 @@ struct SvdParams {
 // Launchers (stream-ordered, asynchronous).
 hipError_t launch_init_product(const DevBatch& b, const uint8_t* d_occ, hipStream_t st);
 // phi[slot][m] = -2 c_m theta[slot][param_m] + (m == shift_rot[slot] ? shift_val[slot] : 0)
+// Copies slot states src -> dst (same shape): pairs[i] = (src slot, dst
+// slot), or the single pair `one` when d_pairs is null.
+hipError_t launch_copy_slots(const DevBatch& src, const DevBatch& dst, const int2* d_pairs, int n_pairs, int2 one,
+                             bool clear_work, hipStream_t st);
 hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d_theta, int n_theta,
                          const int* d_shift_rot, const double* d_shift_val, hipStream_t st);
 hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, const double2* d_pre,

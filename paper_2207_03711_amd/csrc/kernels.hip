@@ -194,6 +194,30 @@ __global__ void k_init_product(DevBatch b, const uint8_t* occ) {
   }
 }
 
+// State copy between slots of two batches of one shape: the site tensors,
+// Schmidt values, bond dimensions, statistics and flags of slot pr.x of src
+// go to slot pr.y of dst, pr = pairs[blockIdx.x] (pairs null: the one pair
+// given).  With clear_work the copy's executed-work counters (FLOPs, sweeps,
+// cycles, SVD path counts) start from zero, so that summing them over slots
+// counts every gate that ran once.
+__global__ void k_copy_slots(DevBatch src, DevBatch dst, const int2* pairs, int2 one, int clear_work) {
+  const int2 pr = pairs ? pairs[blockIdx.x] : one;
+  const int N = src.n_qubits;
+  const long n16 = (src.site_off[N] * (src.mixed ? 8 : 16) + 15) / 16;
+  const uint4* s4 = reinterpret_cast<const uint4*>(src.sites + pr.x * src.site_stride);
+  uint4* d4 = reinterpret_cast<uint4*>(dst.sites + pr.y * dst.site_stride);
+  for (long i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
+  for (long i = threadIdx.x; i < src.lam_off[N - 1]; i += blockDim.x)
+    dst.lam[pr.y * dst.lam_stride + i] = src.lam[pr.x * src.lam_stride + i];
+  for (int i = threadIdx.x; i <= N; i += blockDim.x) dst.chi[pr.y * (N + 1) + i] = src.chi[pr.x * (N + 1) + i];
+  for (int i = threadIdx.x; i < kNStats; i += blockDim.x) {
+    const bool work = i == kStatFlops || i == kStatSweepSum || (i >= kStatCycContract && i <= kStatCycUpdate) ||
+                      i == kStatFallbacks || i == kStatBisect;
+    dst.stats[pr.y * kNStats + i] = (clear_work && work) ? 0.0 : src.stats[pr.x * kNStats + i];
+  }
+  if (threadIdx.x == 0) dst.flags[pr.y] = src.flags[pr.x];
+}
+
 // phi of slots slot0 + y (theta and the shifts are indexed from the launch's first slot)
 __global__ void k_angles(double* phi, int n_rot, const double* rot_c, const int* rot_param,
                          const double* theta, int n_theta, const int* shift_rot, const double* shift_val,
@@ -1695,6 +1719,14 @@ hipError_t launch_init_product(const DevBatch& b, const uint8_t* d_occ, hipStrea
     hipLaunchKernelGGL(k_init_product<float2>, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
   else
     hipLaunchKernelGGL(k_init_product<double2>, dim3(b.n_slots), dim3(64), 0, st, b, d_occ);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_slots(const DevBatch& src, const DevBatch& dst, const int2* d_pairs, int n_pairs, int2 one,
+                             bool clear_work, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_slots, dim3(d_pairs ? n_pairs : 1), dim3(256), 0, st, src, dst, d_pairs, one,
+                     clear_work ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -213,6 +213,41 @@ struct Batch {
   }
 };
 
+// Slot states without workspaces (snapshots of a batch's slots): the site
+// tensors, Schmidt values, bond dimensions, statistics and flags of `slots`
+// slots in the layout of the batch `shape`.
+struct SlotStore {
+  q2c::DevBatch d;
+  std::vector<DBuf> bufs;
+  SlotStore(q2c_ctx* ctx, const q2c::DevBatch& shape, int slots) {
+    const int N = shape.n_qubits;
+    q2c::DevBatch b{};
+    b.n_qubits = N;
+    b.max_bond = shape.max_bond;
+    b.n_slots = slots;
+    b.ws = shape.ws;
+    b.mixed = shape.mixed;
+    for (int i = 0; i <= q2c::kMaxQubits; ++i) {
+      b.cap[i] = shape.cap[i];
+      b.site_off[i] = shape.site_off[i];
+      b.lam_off[i] = shape.lam_off[i];
+    }
+    b.site_stride = shape.site_stride;
+    b.lam_stride = shape.lam_stride;
+    auto alloc = [&](size_t bytes) -> void* {
+      bufs.emplace_back(ctx, bytes);
+      return bufs.back().p;
+    };
+    const size_t S = size_t(slots);
+    b.sites = static_cast<double2*>(alloc(S * b.site_stride * sizeof(double2)));
+    b.lam = static_cast<double*>(alloc(S * b.lam_stride * sizeof(double)));
+    b.chi = static_cast<int*>(alloc(S * (N + 1) * sizeof(int)));
+    b.stats = static_cast<double*>(alloc(S * q2c::kNStats * sizeof(double)));
+    b.flags = static_cast<int*>(alloc(S * sizeof(int)));
+    d = b;
+  }
+};
+
 inline q2c::SvdParams svd_params(const q2c_ctx* ctx) {
   q2c::SvdParams sp;
   sp.max_sweeps = ctx->opts.max_sweeps;

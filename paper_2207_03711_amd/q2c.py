@@ -44,6 +44,7 @@ class q2c_opts(C.Structure):
         ("slots", C.c_int),
         ("hbm_budget_bytes", C.c_size_t),
         ("svd_algorithm", C.c_int),
+        ("shift_from_start", C.c_int),
     ]
 
 

@@ -319,6 +319,40 @@ def test_shift_energies_match_oracle_statevector(q2c, ctx):
     p.close()
 
 
+@pytest.mark.parametrize("D,prec", [(16, "fp64"), (4, "fp64"), (16, "mixed")])
+def test_forked_shifts_equal_from_start(q2c, D, prec):
+    """Shifted circuits started from copies of the unshifted run at their fork
+    gates give the energies of circuits run from the first gate, bit for
+    bit: the full gradient and base energy at 8 qubits over several windows
+    (8 slots, 4 rotations per window), and a shift subset given out of order
+    with a repeated rotation.  The forked run executes about half the gates."""
+    P = q2c.Q2C_FP64 if prec == "fp64" else q2c.Q2C_MIXED
+    cfg = CONFIGS["q8_d16"]
+    I = cfg.integrals()
+    th = cfg.theta()
+    c_fork = q2c.Context(0, slots=8)
+    c_full = q2c.Context(0, slots=8, shift_from_start=1)
+    pf = _problem(q2c, c_fork, I)
+    pa = _problem(q2c, c_full, I)
+    gf, ef, sf = pf.grad(th, D, P)
+    ga, ea, sa = pa.grad(th, D, P)
+    assert np.array_equal(gf, ga) and ef == ea
+    e1, _ = pf.energy(th, D, P)
+    assert ef == e1
+    assert sf["n_circuits"] == sa["n_circuits"] == 2 * pf.info["n_rotations"] + 1
+    assert sf["gate_flops"] < 0.7 * sa["gate_flops"]
+    nrot = pf.info["n_rotations"]
+    idx = [nrot - 1, 3, nrot // 2, 3, 0, nrot // 3]
+    ep1, em1, _ = pf.shift_energies(th, idx, D, P)
+    ep2, em2, _ = pa.shift_energies(th, idx, D, P)
+    assert np.array_equal(ep1, ep2) and np.array_equal(em1, em2)
+    assert ep1[1] == ep1[3] and em1[1] == em1[3]
+    for p_ in (pf, pa):
+        p_.close()
+    c_fork.close()
+    c_full.close()
+
+
 def test_argument_errors_on_device(q2c, ctx):
     I = random_integrals(2, 2, 1)
     p = _problem(q2c, ctx, I)
