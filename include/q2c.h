@@ -79,6 +79,15 @@ typedef struct {
                                from a copy of the unshifted circuit's state at its first
                                angle-dependent gate (same energies, about half the gates);
                                1 -> every circuit runs from the first gate                 */
+  int eager_batches;        /* batched calls (energy batches, parameter shifts): 0 -> each
+                               batch shape is captured once as a HIP graph (inputs, every
+                               kernel, outputs) and replayed; 1 -> launched one by one     */
+  int no_autotune;          /* 0 -> the Pauli sweep's GEMM tile and workgroups per circuit
+                               are chosen by timing the candidates on the first batch of
+                               each shape (results do not depend on the choice);
+                               1 -> fixed defaults                                         */
+  const char* autotune_cache; /* nullable: text file of tuned choices, read at context
+                               creation and appended to; the string is copied            */
 } q2c_opts;
 
 /* Statistics of the last state evolution (all over the gates applied). */
@@ -112,6 +121,12 @@ typedef struct {
   double cycles[6];
   double svd_bisect_gates;     /* gate SVDs done by bisection                               */
   double svd_fallbacks;        /* bisection SVDs that fell back to Jacobi                   */
+  double graph_ms;             /* HIP-event time of replayed batch graphs (whole batches:
+                                  gates, environments, sweeps, reduction, copies)         */
+  int graph_launches;          /* batch graphs replayed                                    */
+  int pauli_tile;              /* Pauli-sweep tile of the last batch (0: 64x64x8,
+                                  1: 64x64x16, 2: 32x32x16)                               */
+  int pauli_wg;                /* Pauli-sweep workgroups per circuit of the last batch     */
 } q2c_stats;
 
 /* Context: one device, one HIP stream.

@@ -38,6 +38,48 @@ struct mps_state {
   int scratch_wg = 0;
 };
 
+// Pinned host memory (hipHostMalloc), the staging area of graph inputs and
+// outputs.
+struct HostBuf {
+  void* p = nullptr;
+  explicit HostBuf(size_t bytes) { hip_check(hipHostMalloc(&p, std::max<size_t>(bytes, 16), 0), "hipHostMalloc"); }
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// One batch shape captured as a HIP graph: the inputs copied from pinned
+// host memory, the angles, the initial states (the Hartree-Fock product, or
+// copies of snapshot slots that start at per-slot fork gates), every gate
+// launch over per-slot gate cursors, the environments, the Pauli sweep, the
+// reduction, and energies, flags and statistics copied back to pinned host
+// memory.  Every buffer the graph touches is its own or lives as long as the
+// problem, so a replay needs only new inputs in the staging area.
+struct BatchGraph {
+  int nb = 0;
+  bool fork = false;
+  bool tuned = false;
+  int launches = 0;  // gate-kernel launches per replay
+  PauliCfg cfg;
+  std::unique_ptr<HostBuf> h_theta, h_srot, h_sval, h_cursor, h_pairs, h_energy, h_flags, h_stats;
+  DBuf theta, srot, sval, cursor, pairs, phi, ev_re, ev_im, scratch, energy;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void release_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~BatchGraph() { release_graph(); }
+};
+
 struct vqe_problem {
   q2c_ctx* ctx = nullptr;
   q2c::Problem host;
@@ -48,6 +90,8 @@ struct vqe_problem {
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
          phi_cap = 0, cursor_cap = 0, pairs_cap = 0;
   std::vector<int> fork_gate;  // per rotation: its first gate whose matrix depends on the rotation's angle
+  std::map<std::tuple<int, int>, std::unique_ptr<SlotStore>> snaps;  // (D, precision): fork snapshots
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<BatchGraph>> graphs;  // (D, slots, precision, fork)
 };
 
 namespace {
@@ -96,6 +140,61 @@ int run_gates(vqe_problem* p, const q2c::DevBatch& db, int g0, int g1, hipStream
   return launches;
 }
 
+Tuner::Key pauli_key(const vqe_problem* p, const q2c::DevBatch& db, int n_slots) {
+  return Tuner::Key{p->host.n_qubits, db.max_bond, n_slots, db.mixed ? Q2C_MIXED : Q2C_FP64, p->dev.n_strings};
+}
+
+size_t pauli_scratch_bytes(const vqe_problem* p, const Batch& B, int n_slots, int n_wg) {
+  return size_t(n_slots) * n_wg * q2c::pauli_scratch_mats(p->host.n_qubits) * size_t(B.cm) * B.cm *
+         sizeof(double2);
+}
+
+// Times every candidate launch of the Pauli sweep (each tile, with half,
+// once and twice the default workgroups per circuit) on the environments
+// already in db, after one untimed launch, and stores the fastest in the
+// context's table.  Outputs go to ev_re / ev_im and are overwritten by the
+// caller's own launch.
+PauliCfg tune_pauli(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, int n_slots, double* ev_re,
+                    double* ev_im, hipStream_t st) {
+  q2c_ctx* ctx = p->ctx;
+  const int ns = p->dev.n_strings;
+  const int base = pauli_workgroups(ns, n_slots);
+  std::vector<int> wgs;
+  for (int w : {base / 2, base, 2 * base}) {
+    w = std::max(1, std::min(w, ns));
+    if (std::find(wgs.begin(), wgs.end(), w) == wgs.end()) wgs.push_back(w);
+  }
+  DBuf scr(ctx, pauli_scratch_bytes(p, B, n_slots, *std::max_element(wgs.begin(), wgs.end())));
+  auto launch = [&](int tile, int w) {
+    hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
+                                scr.as<double2>(), w, B.cm, ev_re, ev_im, tile, st),
+              "pauli (tuning)");
+  };
+  Events ev;
+  launch(0, base);
+  PauliCfg best{0, base, 1e300};
+  for (int tile = 0; tile < q2c::kPauliTiles; ++tile)
+    for (int w : wgs) {
+      hip_check(hipEventRecord(ev.e[0], st), "event");
+      launch(tile, w);
+      hip_check(hipEventRecord(ev.e[1], st), "event");
+      hip_check(hipEventSynchronize(ev.e[1]), "sync");
+      const double ms = ev.ms(0, 1);
+      if (ms < best.ms) best = PauliCfg{tile, w, ms};
+    }
+  ctx->tuner.store(pauli_key(p, db, n_slots), best);
+  return best;
+}
+
+// The Pauli-sweep choice for a batch shape: tuned, or the default when
+// tuning is off; *need_tuning tells whether the shape is still untuned.
+PauliCfg pauli_choice(const vqe_problem* p, const q2c::DevBatch& db, int n_slots, bool* need_tuning) {
+  const PauliCfg* t = p->ctx->tuner.find(pauli_key(p, db, n_slots));
+  *need_tuning = !t && !p->ctx->opts.no_autotune;
+  if (t) return *t;
+  return PauliCfg{0, pauli_workgroups(p->dev.n_strings, n_slots), 0.0};
+}
+
 // Energies of slots 0 .. n_slots-1 of db, whose gates have all run:
 // environments, Pauli sweeps, reduction; reads back energies, flags and
 // statistics and synchronises the stream.
@@ -111,19 +210,22 @@ void finish_circuits(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, in
   const int ns = p->dev.n_strings;
   ensure(ctx, p->ev_re, p->evr_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
   ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
-  const int n_wg = pauli_workgroups(ns, n_slots);
-  const size_t scr =
-      size_t(n_slots) * n_wg * q2c::pauli_scratch_mats(H.n_qubits) * size_t(B.cm) * B.cm * sizeof(double2);
-  ensure(ctx, p->scratch, p->scratch_cap, scr);
-  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
-                              p->scratch.as<double2>(), n_wg, B.cm, p->ev_re.as<double>(), p->ev_im.as<double>(), st),
-            "pauli");
+  bool need_tuning = false;
+  PauliCfg cfg = pauli_choice(p, db, n_slots, &need_tuning);
+  if (need_tuning) cfg = tune_pauli(p, B, db, n_slots, p->ev_re.as<double>(), p->ev_im.as<double>(), st);
+  pt.pauli = cfg;
+  ensure(ctx, p->scratch, p->scratch_cap, pauli_scratch_bytes(p, B, n_slots, cfg.n_wg));
   hip_check(hipEventRecord(ev.e[2], st), "event");
+  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
+                              p->scratch.as<double2>(), cfg.n_wg, B.cm, p->ev_re.as<double>(), p->ev_im.as<double>(),
+                              cfg.tile, st),
+            "pauli");
+  hip_check(hipEventRecord(ev.e[3], st), "event");
   ensure(ctx, p->energies, p->en_cap, sizeof(double) * n_slots);
   hip_check(q2c::launch_energy_reduce(db, p->dev.str_c, p->ev_re.as<double>(), p->ev_im.as<double>(), ns,
                                       H.c_identity, p->energies.as<double>(), st),
             "reduce");
-  hip_check(hipEventRecord(ev.e[3], st), "event");
+  hip_check(hipEventRecord(ev.e[4], st), "event");
   std::vector<int> flags(n_slots);
   stats_out.assign(size_t(n_slots) * q2c::kNStats, 0.0);
   hip_check(hipMemcpyAsync(energies, p->energies.p, sizeof(double) * n_slots, hipMemcpyDeviceToHost, st), "copy E");
@@ -134,8 +236,8 @@ void finish_circuits(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, in
             "copy stats");
   hip_check(hipStreamSynchronize(st), "sync");
   pt.env_ms += ev.ms(0, 1);
-  pt.pauli_ms += ev.ms(1, 2);
-  pt.reduce_ms += ev.ms(2, 3);
+  pt.pauli_ms += ev.ms(2, 3);
+  pt.reduce_ms += ev.ms(3, 4);
   pt.circuits += n_slots;
   check_flags(flags);
   for (int i = 0; i < n_slots; ++i)
@@ -178,6 +280,174 @@ void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int
   finish_circuits(p, B, db, n_slots, energies, stats_out, pt);
   pt.gate_ms += ev.ms(0, 1);
 }
+
+SlotStore& snap_store(vqe_problem* p, int D, int precision, int slots) {
+  auto key = std::make_tuple(D, precision);
+  auto& ss = p->snaps[key];
+  if (!ss || ss->d.n_slots < slots) {
+    for (auto it = p->graphs.begin(); it != p->graphs.end();)  // fork graphs read the old store
+      it = (std::get<0>(it->first) == D && std::get<2>(it->first) == precision && std::get<3>(it->first))
+               ? p->graphs.erase(it)
+               : std::next(it);
+    ss.reset();
+    ss = std::make_unique<SlotStore>(p->ctx, batch_for(p, D, 1, precision).d, slots);
+  }
+  return *ss;
+}
+
+// Enqueues one batch of G on stream cs (the capture stream).
+void enqueue_batch(vqe_problem* p, const Batch& B, BatchGraph& G, const SlotStore* snaps, hipStream_t cs) {
+  const auto& H = p->host;
+  const int nb = G.nb, np = H.n_params, ns = p->dev.n_strings;
+  auto h2d = [&](DBuf& dst, const HostBuf& src, size_t bytes) {
+    hip_check(hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyHostToDevice, cs), "graph input");
+  };
+  if (np) h2d(G.theta, *G.h_theta, sizeof(double) * size_t(nb) * np);
+  h2d(G.srot, *G.h_srot, sizeof(int) * nb);
+  h2d(G.sval, *G.h_sval, sizeof(double) * nb);
+  h2d(G.cursor, *G.h_cursor, sizeof(int) * nb);
+  if (G.fork) h2d(G.pairs, *G.h_pairs, sizeof(int2) * nb);
+  q2c::DevBatch db = B.d;
+  db.phi = G.phi.as<double>();
+  db.cursor = G.cursor.as<int>();
+  db.n_gates = p->dev.n_gates;
+  hip_check(q2c::launch_angles(db, p->dev, G.theta.as<double>(), np, G.srot.as<int>(), G.sval.as<double>(), cs),
+            "angles");
+  if (G.fork)
+    hip_check(q2c::launch_copy_slots(snaps->d, db, G.pairs.as<int2>(), nb, make_int2(0, 0), true, cs), "restore");
+  else
+    hip_check(q2c::launch_init_product(db, p->occ.as<uint8_t>(), cs), "init");
+  const q2c::SvdParams sp = svd_params(p->ctx);
+  G.launches = 0;
+  for (int c0 = 0; c0 < p->dev.n_gates; c0 += kGateChunk, ++G.launches)
+    hip_check(q2c::launch_gates(db, p->dev.gate_site, p->dev.gate_rot, p->dev.gate_pre, p->dev.gate_post, 0,
+                                kGateChunk, p->dev.n_rot, sp, cs),
+              "gates");
+  hip_check(q2c::launch_envs(db, cs), "envs");
+  hip_check(q2c::launch_pauli(db, p->dev.str_x, p->dev.str_z, ns, p->dev.str_order, p->dev.str_share,
+                              G.scratch.as<double2>(), G.cfg.n_wg, B.cm, G.ev_re.as<double>(), G.ev_im.as<double>(),
+                              G.cfg.tile, cs),
+            "pauli");
+  hip_check(q2c::launch_energy_reduce(db, p->dev.str_c, G.ev_re.as<double>(), G.ev_im.as<double>(), ns, H.c_identity,
+                                      G.energy.as<double>(), cs),
+            "reduce");
+  hip_check(hipMemcpyAsync(G.h_energy->p, G.energy.p, sizeof(double) * nb, hipMemcpyDeviceToHost, cs), "graph output");
+  hip_check(hipMemcpyAsync(G.h_flags->p, db.flags, sizeof(int) * nb, hipMemcpyDeviceToHost, cs), "graph output");
+  hip_check(hipMemcpyAsync(G.h_stats->p, db.stats, sizeof(double) * nb * q2c::kNStats, hipMemcpyDeviceToHost, cs),
+            "graph output");
+}
+
+// (Re)captures G with its current Pauli choice on a private stream.
+void capture_graph(vqe_problem* p, const Batch& B, BatchGraph& G, const SlotStore* snaps) {
+  q2c_ctx* ctx = p->ctx;
+  G.release_graph();
+  G.scratch = DBuf(ctx, pauli_scratch_bytes(p, B, G.nb, G.cfg.n_wg));
+  hipStream_t cs = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } guard{cs};
+  hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    enqueue_batch(p, B, G, snaps, cs);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(cs, &G.graph), "hipStreamEndCapture");
+  hip_check(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+// Runs nb circuits through the batch graph of their shape (captured on first
+// use): theta nb x n_params; per slot a shifted rotation (or -1) and shift,
+// a first gate (0, or the fork gate) and, in fork mode, the snapshot slot to
+// start from.  Writes energies and per-slot statistics.  After the first
+// replay of an untuned shape the Pauli sweep is tuned on the live state and
+// the graph re-captured if the choice changed.
+void run_graph(vqe_problem* p, int D, int precision, int nb, bool fork, const double* theta, const int* srot,
+               const double* sval, const int* first_gate, const int* snap_slot, const SlotStore* snaps,
+               double* energies, std::vector<double>& stats_out, PhaseTimes& pt) {
+  q2c_ctx* ctx = p->ctx;
+  ctx->activate();
+  hipStream_t st = ctx->stream;
+  const auto& H = p->host;
+  const int np = H.n_params, ns = p->dev.n_strings;
+  Batch& B = batch_for(p, D, nb, precision);
+  auto key = std::make_tuple(D, nb, precision, fork ? 1 : 0);
+  auto& gp = p->graphs[key];
+  if (!gp) {
+    auto G = std::make_unique<BatchGraph>();
+    G->nb = nb;
+    G->fork = fork;
+    bool need = false;
+    G->cfg = pauli_choice(p, B.d, nb, &need);
+    G->tuned = !need;
+    G->h_theta = std::make_unique<HostBuf>(sizeof(double) * size_t(nb) * std::max(1, np));
+    G->h_srot = std::make_unique<HostBuf>(sizeof(int) * nb);
+    G->h_sval = std::make_unique<HostBuf>(sizeof(double) * nb);
+    G->h_cursor = std::make_unique<HostBuf>(sizeof(int) * nb);
+    G->h_pairs = std::make_unique<HostBuf>(sizeof(int2) * nb);
+    G->h_energy = std::make_unique<HostBuf>(sizeof(double) * nb);
+    G->h_flags = std::make_unique<HostBuf>(sizeof(int) * nb);
+    G->h_stats = std::make_unique<HostBuf>(sizeof(double) * nb * q2c::kNStats);
+    G->theta = DBuf(ctx, sizeof(double) * size_t(nb) * std::max(1, np));
+    G->srot = DBuf(ctx, sizeof(int) * nb);
+    G->sval = DBuf(ctx, sizeof(double) * nb);
+    G->cursor = DBuf(ctx, sizeof(int) * nb);
+    G->pairs = DBuf(ctx, sizeof(int2) * nb);
+    G->phi = DBuf(ctx, sizeof(double) * size_t(nb) * std::max(1, p->dev.n_rot));
+    G->ev_re = DBuf(ctx, sizeof(double) * std::max<size_t>(1, size_t(nb) * ns));
+    G->ev_im = DBuf(ctx, sizeof(double) * std::max<size_t>(1, size_t(nb) * ns));
+    G->energy = DBuf(ctx, sizeof(double) * nb);
+    capture_graph(p, B, *G, snaps);
+    gp = std::move(G);
+  }
+  BatchGraph& G = *gp;
+  // inputs (the previous replay on this stream has completed: every call synchronises)
+  if (np) std::memcpy(G.h_theta->p, theta, sizeof(double) * size_t(nb) * np);
+  for (int i = 0; i < nb; ++i) {
+    G.h_srot->as<int>()[i] = srot ? srot[i] : -1;
+    G.h_sval->as<double>()[i] = sval ? sval[i] : 0.0;
+    G.h_cursor->as<int>()[i] = first_gate ? first_gate[i] : 0;
+    G.h_pairs->as<int2>()[i] = make_int2(snap_slot ? snap_slot[i] : 0, i);
+  }
+  Events ev;
+  hip_check(hipEventRecord(ev.e[0], st), "event");
+  hip_check(hipGraphLaunch(G.exec, st), "hipGraphLaunch");
+  hip_check(hipEventRecord(ev.e[1], st), "event");
+  hip_check(hipStreamSynchronize(st), "sync");
+  pt.graph_ms += ev.ms(0, 1);
+  pt.graph_launches += 1;
+  pt.gate_launches += G.launches;
+  pt.circuits += nb;
+  pt.pauli = G.cfg;
+  std::memcpy(energies, G.h_energy->p, sizeof(double) * nb);
+  std::vector<int> flags(G.h_flags->as<int>(), G.h_flags->as<int>() + nb);
+  stats_out.assign(G.h_stats->as<double>(), G.h_stats->as<double>() + size_t(nb) * q2c::kNStats);
+  if (progress_enabled()) {
+    std::fprintf(stderr, "[q2c] %d circuit(s): batch graph replayed, %.1f s\n", nb, ev.ms(0, 1) / 1e3);
+    std::fflush(stderr);
+  }
+  check_flags(flags);
+  for (int i = 0; i < nb; ++i)
+    if (!std::isfinite(energies[i])) throw StatusError(Q2C_ERR_NUMERIC, "non-finite energy");
+  if (!G.tuned) {
+    q2c::DevBatch db = B.d;
+    const PauliCfg best = tune_pauli(p, B, db, nb, G.ev_re.as<double>(), G.ev_im.as<double>(), st);
+    G.tuned = true;
+    if (best.tile != G.cfg.tile || best.n_wg != G.cfg.n_wg) {
+      G.cfg = best;
+      capture_graph(p, B, G, snaps);
+    } else {
+      G.cfg = best;
+    }
+  }
+}
+
+bool use_graphs(const vqe_problem* p) { return !p->ctx->opts.eager_batches; }
 
 void check_theta(const vqe_problem* p, const double* theta, int n_theta, int count) {
   require(theta != nullptr || p->host.n_params == 0, "theta is NULL");
@@ -232,6 +502,10 @@ int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx**
     require(o.sv_cutoff_rel < 1.0 && o.svd_tol < 1e-3, "bad tolerances");
     require(o.svd_algorithm == 0 || o.svd_algorithm == 1, "svd_algorithm must be 0 or 1");
     require(o.shift_from_start == 0 || o.shift_from_start == 1, "shift_from_start must be 0 or 1");
+    require(o.eager_batches == 0 || o.eager_batches == 1, "eager_batches must be 0 or 1");
+    require(o.no_autotune == 0 || o.no_autotune == 1, "no_autotune must be 0 or 1");
+    c->tuner.load(o.autotune_cache);
+    o.autotune_cache = nullptr;  // the caller's string is not kept
     c->opts = o;
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
@@ -348,7 +622,7 @@ int mps_expect_pauli_batch(mps_state* s, int n_strings, int n_words, const uint6
     hip_check(q2c::launch_envs(B.d, st), "envs");
     hip_check(q2c::launch_pauli(B.d, s->sx.as<uint64_t>(), s->sz.as<uint64_t>(), n_strings, s->sord.as<int>(),
                                 s->sshr.as<int>(), s->scratch.as<double2>(), n_wg, B.cm, s->ev_re.as<double>(),
-                                s->ev_im.as<double>(), st),
+                                s->ev_im.as<double>(), 0, st),
               "pauli");
     hip_check(hipMemcpyAsync(out_re, s->ev_re.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
     if (out_im) hip_check(hipMemcpyAsync(out_im, s->ev_im.p, sizeof(double) * n_strings, hipMemcpyDeviceToHost, st), "copy");
@@ -606,7 +880,12 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
     const int chunk = chunk_slots(p);
     for (int b0 = 0; b0 < n_batch; b0 += chunk) {
       const int nb = std::min(chunk, n_batch - b0);
-      run_circuits(p, max_bond, precision, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st, pt);
+      if (use_graphs(p))
+        run_graph(p, max_bond, precision, nb, false, theta + size_t(b0) * n_theta, nullptr, nullptr, nullptr, nullptr,
+                  nullptr, out.data() + b0, st, pt);
+      else
+        run_circuits(p, max_bond, precision, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st,
+                     pt);
       all_st.insert(all_st.end(), st.begin(), st.end());
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -643,7 +922,12 @@ void shift_energies_from_start(vqe_problem* p, const double* theta, const std::v
   for (int b0 = 0; b0 < total; b0 += chunk) {
     const int nb = std::min(chunk, total - b0);
     for (int i = 0; i < nb; ++i) std::copy(theta, theta + np, th.begin() + size_t(i) * np);
-    run_circuits(p, max_bond, precision, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st, pt);
+    if (use_graphs(p))
+      run_graph(p, max_bond, precision, nb, false, th.data(), srot.data() + b0, sval.data() + b0, nullptr, nullptr,
+                nullptr, en.data() + b0, st, pt);
+    else
+      run_circuits(p, max_bond, precision, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st,
+                   pt);
     all_st.insert(all_st.end(), st.begin(), st.end());
   }
 }
@@ -674,7 +958,7 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
 
   // base slot: the unshifted circuit
   Batch& base = batch_for(p, max_bond, 1, precision);
-  SlotStore snaps(ctx, base.d, std::min(W, std::max(1, nr)));
+  SlotStore& snaps = snap_store(p, max_bond, precision, W);
   ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, 2 * W) * np));
   ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(2 * W) * std::max(1, p->dev.n_rot));
   DBuf base_phi(ctx, sizeof(double) * std::max(1, p->dev.n_rot));
@@ -697,10 +981,8 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
       hip_check(q2c::launch_copy_slots(bd, snaps.d, nullptr, 1, make_int2(0, i), false, st), "snapshot");
     }
     // the window's shifted circuits, each from its copy and fork gate
-    Batch& B = batch_for(p, max_bond, nb, precision);
-    q2c::DevBatch db = B.d;
     std::vector<double> th(size_t(nb) * np), sval(nb);
-    std::vector<int> srot(nb), cursor(nb);
+    std::vector<int> srot(nb), cursor(nb), snap_slot(nb);
     std::vector<int2> pairs(nb);
     for (int j = 0; j < nb; ++j) {
       const int m = rots[ord[w0 + j / 2]];
@@ -708,8 +990,21 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
       srot[j] = m;
       sval[j] = (j % 2 == 0 ? 0.5 : -0.5) * M_PI;
       cursor[j] = p->fork_gate[m];
+      snap_slot[j] = j / 2;
       pairs[j] = make_int2(j / 2, j);
     }
+    e_batch.resize(nb);
+    if (use_graphs(p)) {
+      hip_check(hipEventRecord(ev.e[1], st), "event");
+      run_graph(p, max_bond, precision, nb, true, th.data(), srot.data(), sval.data(), cursor.data(),
+                snap_slot.data(), &snaps, e_batch.data(), st_batch, pt);
+      pt.gate_ms += ev.ms(0, 1);
+      for (int j = 0; j < nb; ++j) en[2 * ord[w0 + j / 2] + (j % 2)] = e_batch[j];
+      all_st.insert(all_st.end(), st_batch.begin(), st_batch.end());
+      continue;
+    }
+    Batch& B = batch_for(p, max_bond, nb, precision);
+    q2c::DevBatch db = B.d;
     ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * nb);
     ensure(ctx, p->shift_val, p->sval_cap, sizeof(double) * nb);
     ensure(ctx, p->cursor, p->cursor_cap, sizeof(int) * nb);
@@ -729,7 +1024,6 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
     const int left = n_gates - p->fork_gate[rots[ord[w0]]];
     pt.gate_launches += run_gates(p, db, 0, left, st);
     hip_check(hipEventRecord(ev.e[1], st), "event");
-    e_batch.resize(nb);
     finish_circuits(p, B, db, nb, e_batch.data(), st_batch, pt);
     pt.gate_ms += ev.ms(0, 1);
     for (int j = 0; j < nb; ++j) en[2 * ord[w0 + j / 2] + (j % 2)] = e_batch[j];

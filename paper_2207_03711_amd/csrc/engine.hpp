@@ -108,9 +108,12 @@ hipError_t launch_envs(const DevBatch& b, hipStream_t st);
 // workgroup takes a contiguous run of ceil(n_strings / n_wg) sorted strings.
 // d_scratch: n_slots * n_wg * pauli_scratch_mats(N) * cm * cm double2,
 // cm = largest bond cap.
+// tile: 0 .. kPauliTiles-1, the GEMM tile of the transfers (64x64x8,
+// 64x64x16, 32x32x16); every tile gives the same results bit for bit.
+constexpr int kPauliTiles = 3;
 hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings,
                         const int* d_order, const int* d_share, double2* d_scratch, int n_wg, int cm,
-                        double* d_ev_re, double* d_ev_im, hipStream_t st);
+                        double* d_ev_re, double* d_ev_im, int tile, hipStream_t st);
 inline int pauli_scratch_mats(int n_qubits) { return n_qubits + 2; }
 hipError_t launch_energy_reduce(const DevBatch& b, const double* d_coeff, const double* d_ev_re,
                                 const double* d_ev_im, int n_strings, double c_identity,

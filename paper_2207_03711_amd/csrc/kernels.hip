@@ -71,6 +71,77 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Block-level complex GEMM with a chosen tile: C = alpha * op(A) * op(B)
+// (+ C if accumulate), operands as in bgemm below.
+// 512 threads as 16 x 32; tile BM x BN (BM = 32 RM, BN = 16 RN) over K in
+// steps of BK, staged in lds: (BM + BN) * BK elements.  Every output is
+// summed over k in ascending order, whatever the tile, so all tiles give the
+// same result bit for bit.  All threads of the block must call it.
+template <bool TA, bool TB, typename T, int BM, int BN, int BK>
+__device__ void bgemm_tiled(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
+                            T* __restrict__ C, int ldc, T alpha, bool accumulate, T* lds) {
+  static_assert(BM % 32 == 0 && BN % 16 == 0, "tile must cover the 16 x 32 thread grid");
+  constexpr int RM = BM / 32, RN = BN / 16;
+  T* As = lds;
+  T* Bs = lds + BK * BM;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;  // 16 x 32 threads
+  __syncthreads();
+  for (int i0 = 0; i0 < M; i0 += BM) {
+    for (int j0 = 0; j0 < N; j0 += BN) {
+      T acc[RM][RN];
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int q = 0; q < RN; ++q) acc[r][q] = cval<T>(0.0, 0.0);
+      for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (unsigned e = tid; e < unsigned(BM * BK); e += 512) {
+          const int r = int(e / BK), k = int(e % BK);
+          const int gi = i0 + r, gk = k0 + k;
+          T v = cval<T>(0.0, 0.0);
+          if (gi < M && gk < K) v = TA ? cconj(A[(long)gk * lda + gi]) : A[(long)gi * lda + gk];
+          As[k * BM + r] = v;
+        }
+#pragma unroll
+        for (unsigned e = tid; e < unsigned(BK * BN); e += 512) {
+          const int k = int(e / BN), c = int(e % BN);
+          const int gk = k0 + k, gj = j0 + c;
+          T v = cval<T>(0.0, 0.0);
+          if (gk < K && gj < N) v = TB ? cconj(B[(long)gj * ldb + gk]) : B[(long)gk * ldb + gj];
+          Bs[k * BN + c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+          T a[RM];
+#pragma unroll
+          for (int r = 0; r < RM; ++r) a[r] = As[k * BM + ty * RM + r];
+#pragma unroll
+          for (int q = 0; q < RN; ++q) {
+            const T bv = Bs[k * BN + tx * RN + q];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) cfma(acc[r][q], a[r], bv);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int q = 0; q < RN; ++q) {
+          const int gi = i0 + ty * RM + r, gj = j0 + tx * RN + q;
+          if (gi < M && gj < N) {
+            T v = cmul(alpha, acc[r][q]);
+            T* dst = &C[(long)gi * ldc + gj];
+            *dst = accumulate ? cadd(*dst, v) : v;
+          }
+        }
+    }
+  }
+  __syncthreads();
+}
+
 // Block-level complex GEMM: C = alpha * op(A) * op(B) (+ C if accumulate).
 // op(A)[i][k] = TA ? conj(A[k*lda+i]) : A[i*lda+k]
 // op(B)[k][j] = TB ? conj(B[j*ldb+k]) : B[k*ldb+j]
@@ -1617,12 +1688,12 @@ __global__ __launch_bounds__(kBlock) void k_envs(DevBatch b) {
 // keeps a stack of partial left transfers and recomputes only the rest (the
 // prefix trie of the strings, one node per transfer step).  Without order,
 // strings go in their own order with no reuse.
-template <typename S>
+template <typename S, int BM, int BN, int BK>
 __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __restrict__ sx,
                                                   const uint64_t* __restrict__ sz, int n_strings,
                                                   const int* __restrict__ order, const int* __restrict__ share,
                                                   double2* scratch, int cm, double* ev_re, double* ev_im) {
-  __shared__ S lds_gemm[2 * 64 * 8];
+  __shared__ S lds_gemm[(BM + BN) * BK];
   __shared__ double red[kBlock / 64];
   const int r = blockIdx.y, slot = b.slot0 + r;  // outputs and scratch are indexed from the first slot
   const int N = b.n_qubits;
@@ -1660,9 +1731,10 @@ __global__ __launch_bounds__(kBlock) void k_pauli(DevBatch b, const uint64_t* __
           S ph = cval<S>(1.0, 0.0);
           if (zb && !xb) ph = cval<S>(i == 0 ? 1.0 : -1.0, 0.0);  // Z
           if (zb && xb) ph = cval<S>(0.0, i == 0 ? -1.0 : 1.0);   // Y: <0|Y|1> = -i
-          bgemm<false, false, S>(cl, cr, cl, T, ldt, Bk + ip * capr, 2 * capr, X, cm, cval<S>(1.0, 0.0), false,
-                                 lds_gemm);
-          bgemm<true, false, S>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1, lds_gemm);
+          bgemm_tiled<false, false, S, BM, BN, BK>(cl, cr, cl, T, ldt, Bk + ip * capr, 2 * capr, X, cm,
+                                                   cval<S>(1.0, 0.0), false, lds_gemm);
+          bgemm_tiled<true, false, S, BM, BN, BK>(cr, cr, cl, Bk + i * capr, 2 * capr, X, cm, Tn, cm, ph, i == 1,
+                                                  lds_gemm);
         }
       }
       // <P> = sum_{c,c'} T[c][c'] R[c][c'],  R[c][c'] = Rt[c'][c]
@@ -1768,16 +1840,36 @@ hipError_t launch_envs(const DevBatch& b, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename S>
+static void launch_pauli_t(int tile, dim3 grid, hipStream_t st, const DevBatch& b, const uint64_t* d_x,
+                           const uint64_t* d_z, int n_strings, const int* d_order, const int* d_share,
+                           double2* d_scratch, int cm, double* d_ev_re, double* d_ev_im) {
+  switch (tile) {
+    case 1:
+      hipLaunchKernelGGL((k_pauli<S, 64, 64, 16>), grid, dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
+                         d_share, d_scratch, cm, d_ev_re, d_ev_im);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_pauli<S, 32, 32, 16>), grid, dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
+                         d_share, d_scratch, cm, d_ev_re, d_ev_im);
+      break;
+    default:
+      hipLaunchKernelGGL((k_pauli<S, 64, 64, 8>), grid, dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
+                         d_share, d_scratch, cm, d_ev_re, d_ev_im);
+  }
+}
+
 hipError_t launch_pauli(const DevBatch& b, const uint64_t* d_x, const uint64_t* d_z, int n_strings, const int* d_order,
                         const int* d_share, double2* d_scratch, int n_wg, int cm, double* d_ev_re, double* d_ev_im,
-                        hipStream_t st) {
+                        int tile, hipStream_t st) {
   if (n_strings == 0) return hipSuccess;
+  if (tile < 0 || tile >= kPauliTiles) return hipErrorInvalidValue;
+  const dim3 grid(n_wg, b.n_slots);
   if (b.mixed)
-    hipLaunchKernelGGL(k_pauli<float2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
-                       d_share, d_scratch, cm, d_ev_re, d_ev_im);
+    launch_pauli_t<float2>(tile, grid, st, b, d_x, d_z, n_strings, d_order, d_share, d_scratch, cm, d_ev_re, d_ev_im);
   else
-    hipLaunchKernelGGL(k_pauli<double2>, dim3(n_wg, b.n_slots), dim3(kBlock), 0, st, b, d_x, d_z, n_strings, d_order,
-                       d_share, d_scratch, cm, d_ev_re, d_ev_im);
+    launch_pauli_t<double2>(tile, grid, st, b, d_x, d_z, n_strings, d_order, d_share, d_scratch, cm, d_ev_re,
+                            d_ev_im);
   return hipGetLastError();
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -87,12 +89,63 @@ inline void require(bool ok, const char* msg) {
 using q2c_rt::hip_check;
 using q2c_rt::OomError;
 
+namespace q2c_rt {
+
+// Launch choice of the Pauli sweep for one batch shape.
+struct PauliCfg {
+  int tile = 0;    // launch_pauli tile index
+  int n_wg = 1;    // workgroups per circuit
+  double ms = 0.0; // time measured when tuned (0: default, not measured)
+};
+
+// Tuned launch choices by batch shape (qubits, D, circuits, precision,
+// strings), filled by timing every candidate on live data the first time a
+// shape is seen; the choice never changes results, only time.  Entries can
+// be read from and appended to a text file, one per line:
+//   pauli n_qubits max_bond slots precision n_strings tile n_wg ms
+struct Tuner {
+  using Key = std::array<int, 5>;
+  std::map<Key, PauliCfg> pauli;
+  std::string path;
+
+  void load(const char* file) {
+    if (!file || !*file) return;
+    path = file;
+    std::FILE* f = std::fopen(file, "r");
+    if (!f) return;  // created on the first store
+    char kind[16];
+    int k[5], tile, wg;
+    double ms;
+    while (std::fscanf(f, "%15s %d %d %d %d %d %d %d %lf", kind, &k[0], &k[1], &k[2], &k[3], &k[4], &tile, &wg,
+                       &ms) == 9) {
+      if (std::strcmp(kind, "pauli") == 0 && tile >= 0 && tile < q2c::kPauliTiles && wg >= 1 && wg <= k[4])
+        pauli[Key{k[0], k[1], k[2], k[3], k[4]}] = PauliCfg{tile, wg, ms};
+    }
+    std::fclose(f);
+  }
+  const PauliCfg* find(const Key& k) const {
+    auto it = pauli.find(k);
+    return it == pauli.end() ? nullptr : &it->second;
+  }
+  void store(const Key& k, const PauliCfg& c) {
+    pauli[k] = c;
+    if (path.empty()) return;
+    if (std::FILE* f = std::fopen(path.c_str(), "a")) {
+      std::fprintf(f, "pauli %d %d %d %d %d %d %d %.6f\n", k[0], k[1], k[2], k[3], k[4], c.tile, c.n_wg, c.ms);
+      std::fclose(f);
+    }
+  }
+};
+
+}  // namespace q2c_rt
+
 struct q2c_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   q2c_opts opts{};
   size_t bytes_in_use = 0;
+  q2c_rt::Tuner tuner;
 
   void activate() const { hip_check(hipSetDevice(device), "hipSetDevice"); }
 
@@ -259,8 +312,9 @@ inline q2c::SvdParams svd_params(const q2c_ctx* ctx) {
 
 // HIP-event times and launch counts of the device phases of a call.
 struct PhaseTimes {
-  double gate_ms = 0, env_ms = 0, pauli_ms = 0, reduce_ms = 0;
-  int gate_launches = 0, circuits = 0;
+  double gate_ms = 0, env_ms = 0, pauli_ms = 0, reduce_ms = 0, graph_ms = 0;
+  int gate_launches = 0, circuits = 0, graph_launches = 0;
+  PauliCfg pauli;
 };
 
 struct Events {
@@ -303,6 +357,10 @@ inline void fill_stats(q2c_stats* out, const std::vector<double>& st, int slots,
   s.reduce_ms = pt.reduce_ms;
   s.gate_launches = pt.gate_launches;
   s.n_circuits = pt.circuits;
+  s.graph_ms = pt.graph_ms;
+  s.graph_launches = pt.graph_launches;
+  s.pauli_tile = pt.pauli.tile;
+  s.pauli_wg = pt.pauli.n_wg;
   *out = s;
 }
 

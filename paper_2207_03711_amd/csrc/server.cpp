@@ -214,7 +214,7 @@ void finish(q2c_server* s, SrvClass& c, int slot) {
   const int n_wg = std::min(c.n_wg, pauli_workgroups(ns, 1));
   hip_check(q2c::launch_pauli(b, r.sx.as<uint64_t>(), r.sz.as<uint64_t>(), ns, r.sord.as<int>(), r.sshr.as<int>(),
                               c.scratch.as<double2>(), n_wg, c.batch->cm, c.ev_re.as<double>(), c.ev_im.as<double>(),
-                              st),
+                              0, st),
             "pauli");
   hip_check(q2c::launch_energy_reduce(b, r.sc.as<double>(), c.ev_re.as<double>(), c.ev_im.as<double>(), ns,
                                       r.prob.c_identity, c.energy.as<double>(), st),

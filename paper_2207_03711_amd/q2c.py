@@ -45,6 +45,9 @@ class q2c_opts(C.Structure):
         ("hbm_budget_bytes", C.c_size_t),
         ("svd_algorithm", C.c_int),
         ("shift_from_start", C.c_int),
+        ("eager_batches", C.c_int),
+        ("no_autotune", C.c_int),
+        ("autotune_cache", C.c_char_p),
     ]
 
 
@@ -68,6 +71,10 @@ class q2c_stats(C.Structure):
         ("cycles", C.c_double * 6),
         ("svd_bisect_gates", C.c_double),
         ("svd_fallbacks", C.c_double),
+        ("graph_ms", C.c_double),
+        ("graph_launches", C.c_int),
+        ("pauli_tile", C.c_int),
+        ("pauli_wg", C.c_int),
     ]
 
     PHASES = ("contract", "reduce", "values", "vectors", "back", "update")
@@ -360,6 +367,8 @@ class Context:
     def __init__(self, device: int = 0, hip_stream: int | None = None, **opts):
         o = q2c_opts()
         for k, v in opts.items():
+            if isinstance(v, str):
+                v = v.encode()  # the library copies the string during the call
             setattr(o, k, v)
         self.h = q2c_ctx_create(device, hip_stream, o)
 

@@ -1,0 +1,135 @@
+"""GPU: batched execution -- captured batch graphs, their replays and the
+Pauli-sweep autotuner.
+
+Every replay of a captured batch must give, bit for bit, what the same
+batch launched kernel by kernel gives; replays are interleaved with eager
+work (single evaluations, synchronisations) and each is checked.  The tuner
+may only change time: every Pauli tile, forced through the tuning cache
+file, gives the same energies.
+"""
+import numpy as np
+import pytest
+
+from oracle import fermion, statevector as sv, uccsd
+from workloads import CONFIGS, n_uccsd_params, random_integrals, random_theta
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q2c():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_03711_amd import q2c as mod
+
+    return mod
+
+
+def _problem(q2c, ctx, I):
+    return q2c.Problem(ctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_equal_eager(q2c, prec):
+    """Energy batches of 4 circuits (two replays of one graph, then a graph
+    of 2) against the same batches launched eagerly, with single eager
+    evaluations between the replays; truncated (D = 6) 8-qubit circuits."""
+    P = q2c.Q2C_FP64 if prec == "fp64" else q2c.Q2C_MIXED
+    I = CONFIGS["q8_d16"].integrals()
+    cg = q2c.Context(0, slots=4)
+    ce = q2c.Context(0, slots=4, eager_batches=1)
+    pg, pe = _problem(q2c, cg, I), _problem(q2c, ce, I)
+    rng = np.random.default_rng(8)
+    np_ = pg.info["n_params"]
+    for rep in range(3):
+        thetas = rng.uniform(-0.2, 0.2, size=(10, np_))
+        eg, sg = pg.energy_batch(thetas, 6, P)
+        ee, se = pe.energy_batch(thetas, 6, P)
+        assert np.array_equal(eg, ee), (rep, eg - ee)
+        assert sg["graph_launches"] == 3 and se["graph_launches"] == 0
+        assert sg["n_circuits"] == se["n_circuits"] == 10
+        assert sg["gate_flops"] == se["gate_flops"]
+        e1, _ = pg.energy(thetas[rep], 6, P)  # eager work between replays
+        assert e1 == eg[rep]
+    for p_ in (pg, pe):
+        p_.close()
+    cg.close()
+    ce.close()
+
+
+def test_graph_gradient_equals_eager_from_start(q2c):
+    """The parameter-shift gradient through forked batch graphs equals the
+    eager from-start gradient bit for bit, and at full bond dimension the
+    state-vector adjoint gradient to 1e-9 (6 qubits, 6 slots)."""
+    I = random_integrals(3, 2, 4)
+    th = random_theta(n_uccsd_params(3, 2), 12, amp=0.3)
+    cg = q2c.Context(0, slots=6)
+    ce = q2c.Context(0, slots=6, eager_batches=1, shift_from_start=1)
+    pg, pe = _problem(q2c, cg, I), _problem(q2c, ce, I)
+    gg, eg, sg = pg.grad(th, 8)
+    ge, ee, se = pe.grad(th, 8)
+    assert np.array_equal(gg, ge) and eg == ee
+    assert sg["graph_launches"] > 1 and se["graph_launches"] == 0
+    n = 6
+    c_id, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri))
+    rots = uccsd.rotations(n, 2)
+    g_ref, _, e_ref = sv.grad_adjoint(n, 2, c_id, terms, rots, th)
+    assert abs(eg - I.e_const - e_ref) < 1e-10
+    assert np.max(np.abs(gg - g_ref)) < 1e-9
+    gg2, _, _ = pg.grad(th, 8)  # second call: every window is a replay
+    assert np.array_equal(gg2, gg)
+    for p_ in (pg, pe):
+        p_.close()
+    cg.close()
+    ce.close()
+
+
+def test_pauli_tiles_equal_and_cache(q2c, tmp_path):
+    """Each Pauli tile and workgroup count, forced through the cache file,
+    gives the same energies bit for bit; a context tuning into a fresh
+    cache file writes one entry per batch shape, which a new context reads
+    back and uses."""
+    cfg = CONFIGS["q8_d16"]
+    I = cfg.integrals()
+    rng = np.random.default_rng(2)
+    ref = None
+    c0 = q2c.Context(0, slots=3, no_autotune=1)
+    p0 = _problem(q2c, c0, I)
+    ns = p0.info["n_strings"]
+    thetas = rng.uniform(-0.2, 0.2, size=(3, p0.info["n_params"]))
+    ref, s0 = p0.energy_batch(thetas, 16)
+    assert s0["pauli_tile"] == 0
+    p0.close()
+    c0.close()
+    for tile in range(3):
+        for wg in (1, 7, 64):
+            f = tmp_path / f"forced_{tile}_{wg}.txt"
+            f.write_text(f"pauli 8 16 3 0 {ns} {tile} {wg} 0.0\n")
+            c = q2c.Context(0, slots=3, autotune_cache=str(f))
+            p = _problem(q2c, c, I)
+            e, st = p.energy_batch(thetas, 16)
+            assert (st["pauli_tile"], st["pauli_wg"]) == (tile, wg)
+            assert np.array_equal(e, ref), (tile, wg)
+            p.close()
+            c.close()
+    f = tmp_path / "tuned.txt"
+    c = q2c.Context(0, slots=3, autotune_cache=str(f))
+    p = _problem(q2c, c, I)
+    e, _ = p.energy_batch(thetas, 16)
+    e2, st2 = p.energy_batch(thetas, 16)
+    assert np.array_equal(e, ref) and np.array_equal(e2, ref)
+    p.close()
+    c.close()
+    lines = [l.split() for l in f.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0][:6] == ["pauli", "8", "16", "3", "0", str(ns)]
+    assert (int(lines[0][6]), int(lines[0][7])) == (st2["pauli_tile"], st2["pauli_wg"])
+    c = q2c.Context(0, slots=3, autotune_cache=str(f))
+    p = _problem(q2c, c, I)
+    e3, st3 = p.energy_batch(thetas, 16)
+    assert np.array_equal(e3, ref)
+    assert (st3["pauli_tile"], st3["pauli_wg"]) == (st2["pauli_tile"], st2["pauli_wg"])
+    p.close()
+    c.close()
+    assert len(f.read_text().splitlines()) == 1
