@@ -184,6 +184,26 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
     }
 
 
+def q2c_gates(prob):
+    from paper_2207_03711_amd import q2c
+
+    return q2c.vqe_problem_gates(prob.h)
+
+
+def forked_gate_fraction(prob, slots):
+    """Gate launches' work of the forked parameter-shift schedule relative to
+    running every shifted circuit from the first gate: rotations in order of
+    their first angle-dependent gate f_m, slots/2 per batch, each batch
+    running n_gates - min f over its rotations."""
+    _, rot, _, _ = q2c_gates(prob)
+    rot = np.asarray(rot)
+    n_gates = len(rot)
+    fork = np.sort(np.array([np.flatnonzero(rot == m)[0] for m in range(prob.info["n_rotations"])]))
+    w = max(1, slots // 2)
+    work = sum((n_gates - fork[i]) * min(w, len(fork) - i) for i in range(0, len(fork), w))
+    return work / (n_gates * len(fork))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +216,9 @@ def main():
                     help="circuits in the batched measurement (0 to skip)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve", type=int, default=64, help="measured requests of the serving run (0 to skip)")
+    ap.add_argument("--grad", choices=("fp64", "mixed"), default=None,
+                    help="also measure the full parameter-shift gradient of the workload at this precision "
+                         "(2 circuits per rotation + 1, batches of --batch circuits; minutes at 16 qubits)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -324,17 +347,50 @@ def main():
         eb, stb = bprob.energy_batch(thetas, cfg.max_bond)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        ach = stb["gate_flops"] / (stb["gate_ms"] * 1e-3) / 1e12
+        # one captured batch graph: its HIP-event time covers the gates and the (small) sweeps
+        dev_ms = stb["graph_ms"] if stb["graph_launches"] else stb["gate_ms"]
+        ach = stb["gate_flops"] / (dev_ms * 1e-3) / 1e12
         log(f"batched: {args.batch} circuits {dt:.2f}s")
+        fork_frac = forked_gate_fraction(prob, args.batch)
         out["batched"] = {
             "circuits": args.batch, "value": args.batch / dt, "unit": "evals/s", "seconds": dt,
+            "graph_launches": stb["graph_launches"], "pauli_tile": stb["pauli_tile"], "pauli_wg": stb["pauli_wg"],
+            "tune_seconds": stb["tune_ms"] / 1e3,
             "energy_slot0_minus_single": float(eb[0] - energies[-1]),
             "roofline": {"kernel": "k_gates", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS},
-            "gradient_seconds_est": (2 * prob.info["n_rotations"] + 1) / (args.batch / dt),
+                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+                         "time": "batch-graph HIP events (gates + environments + sweeps)"},
+            "gradient_seconds_est_from_start": (2 * prob.info["n_rotations"] + 1) / (args.batch / dt),
+            "gradient_seconds_est_forked": fork_frac * (2 * prob.info["n_rotations"]) / (args.batch / dt)
+            + out["ms_per_step"] / 1e3,
         }
         bprob.close()
         bctx.close()
+    if args.grad:
+        prec = q2c.Q2C_FP64 if args.grad == "fp64" else q2c.Q2C_MIXED
+        gctx = q2c.Context(0, slots=max(2, args.batch))
+        gprob = q2c.Problem(gctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+        log(f"gradient ({args.grad}) ...")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, e_g, stg = gprob.grad(th, cfg.max_bond, prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dev_ms = stg["graph_ms"] + stg["gate_ms"]
+        ach = stg["gate_flops"] / (dev_ms * 1e-3) / 1e12
+        log(f"gradient: {dt:.1f}s, {stg['n_circuits']} circuits")
+        out["gradient"] = {
+            "precision": args.grad, "seconds": dt, "circuits": stg["n_circuits"],
+            "circuits_per_s": stg["n_circuits"] / dt, "graph_launches": stg["graph_launches"],
+            "tune_seconds": stg["tune_ms"] / 1e3,
+            "from_start_seconds_est": out.get("batched", {}).get("gradient_seconds_est_from_start"),
+            "energy": e_g, "grad_norm": float(np.linalg.norm(g)),
+            "roofline": {"kernel": "k_gates", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+                         "flops": "executed gates only (shared prefixes once)"},
+        }
+        gprob.close()
+        gctx.close()
     if args.serve > 0:
         log("serving stream ...")
         out["serving"] = serve_bench(q2c, args.serve)

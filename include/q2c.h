@@ -127,6 +127,9 @@ typedef struct {
   int pauli_tile;              /* Pauli-sweep tile of the last batch (0: 64x64x8,
                                   1: 64x64x16, 2: 32x32x16)                               */
   int pauli_wg;                /* Pauli-sweep workgroups per circuit of the last batch     */
+  double tune_ms;              /* wall time spent autotuning during the call (first use of
+                                  a batch shape; candidates are timed only when one sweep
+                                  takes at most 50 ms)                                     */
 } q2c_stats;
 
 /* Context: one device, one HIP stream.

@@ -130,7 +130,7 @@ int run_gates(vqe_problem* p, const q2c::DevBatch& db, int g0, int g1, hipStream
                                 db.cursor ? 0 : c0, db.cursor ? c1 - c0 : c1, p->dev.n_rot, sp, st),
               "gates");
     ++launches;
-    if (progress_enabled()) {
+    if (progress_enabled() && g1 - g0 >= 1024) {
       hip_check(hipStreamSynchronize(st), "sync");
       std::fprintf(stderr, "[q2c] %d circuit(s): gates %d/%d done, %.1f s\n", db.n_slots, c1, g1,
                    std::chrono::duration<double>(std::chrono::steady_clock::now() - tp0).count());
@@ -149,13 +149,25 @@ size_t pauli_scratch_bytes(const vqe_problem* p, const Batch& B, int n_slots, in
          sizeof(double2);
 }
 
+// Tuning is skipped (the default is kept and recorded) when one default
+// sweep takes longer than this: there the sweep is a small part of a batch
+// whose gates take seconds, and timing every candidate would cost more than
+// it could save.
+constexpr double kTuneMaxMs = 50.0;
+
 // Times every candidate launch of the Pauli sweep (each tile, with half,
 // once and twice the default workgroups per circuit) on the environments
 // already in db, after one untimed launch, and stores the fastest in the
 // context's table.  Outputs go to ev_re / ev_im and are overwritten by the
-// caller's own launch.
+// caller's own launch.  Adds the time spent to *tune_ms.
 PauliCfg tune_pauli(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, int n_slots, double* ev_re,
-                    double* ev_im, hipStream_t st) {
+                    double* ev_im, hipStream_t st, double* tune_ms) {
+  const auto t0 = std::chrono::steady_clock::now();
+  struct AddTime {
+    std::chrono::steady_clock::time_point t0;
+    double* out;
+    ~AddTime() { *out += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); }
+  } add_time{t0, tune_ms};
   q2c_ctx* ctx = p->ctx;
   const int ns = p->dev.n_strings;
   const int base = pauli_workgroups(ns, n_slots);
@@ -171,8 +183,16 @@ PauliCfg tune_pauli(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, int
               "pauli (tuning)");
   };
   Events ev;
+  hip_check(hipEventRecord(ev.e[0], st), "event");
   launch(0, base);
-  PauliCfg best{0, base, 1e300};
+  hip_check(hipEventRecord(ev.e[1], st), "event");
+  hip_check(hipEventSynchronize(ev.e[1]), "sync");
+  PauliCfg best{0, base, ev.ms(0, 1)};
+  if (best.ms > kTuneMaxMs) {
+    p->ctx->tuner.store(pauli_key(p, db, n_slots), best);
+    return best;
+  }
+  best.ms = 1e300;
   for (int tile = 0; tile < q2c::kPauliTiles; ++tile)
     for (int w : wgs) {
       hip_check(hipEventRecord(ev.e[0], st), "event");
@@ -212,7 +232,8 @@ void finish_circuits(vqe_problem* p, const Batch& B, const q2c::DevBatch& db, in
   ensure(ctx, p->ev_im, p->evi_cap, sizeof(double) * std::max<size_t>(1, size_t(n_slots) * ns));
   bool need_tuning = false;
   PauliCfg cfg = pauli_choice(p, db, n_slots, &need_tuning);
-  if (need_tuning) cfg = tune_pauli(p, B, db, n_slots, p->ev_re.as<double>(), p->ev_im.as<double>(), st);
+  if (need_tuning)
+    cfg = tune_pauli(p, B, db, n_slots, p->ev_re.as<double>(), p->ev_im.as<double>(), st, &pt.tune_ms);
   pt.pauli = cfg;
   ensure(ctx, p->scratch, p->scratch_cap, pauli_scratch_bytes(p, B, n_slots, cfg.n_wg));
   hip_check(hipEventRecord(ev.e[2], st), "event");
@@ -436,7 +457,7 @@ void run_graph(vqe_problem* p, int D, int precision, int nb, bool fork, const do
     if (!std::isfinite(energies[i])) throw StatusError(Q2C_ERR_NUMERIC, "non-finite energy");
   if (!G.tuned) {
     q2c::DevBatch db = B.d;
-    const PauliCfg best = tune_pauli(p, B, db, nb, G.ev_re.as<double>(), G.ev_im.as<double>(), st);
+    const PauliCfg best = tune_pauli(p, B, db, nb, G.ev_re.as<double>(), G.ev_im.as<double>(), st, &pt.tune_ms);
     G.tuned = true;
     if (best.tile != G.cfg.tile || best.n_wg != G.cfg.n_wg) {
       G.cfg = best;

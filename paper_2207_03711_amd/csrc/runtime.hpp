@@ -312,7 +312,7 @@ inline q2c::SvdParams svd_params(const q2c_ctx* ctx) {
 
 // HIP-event times and launch counts of the device phases of a call.
 struct PhaseTimes {
-  double gate_ms = 0, env_ms = 0, pauli_ms = 0, reduce_ms = 0, graph_ms = 0;
+  double gate_ms = 0, env_ms = 0, pauli_ms = 0, reduce_ms = 0, graph_ms = 0, tune_ms = 0;
   int gate_launches = 0, circuits = 0, graph_launches = 0;
   PauliCfg pauli;
 };
@@ -361,6 +361,7 @@ inline void fill_stats(q2c_stats* out, const std::vector<double>& st, int slots,
   s.graph_launches = pt.graph_launches;
   s.pauli_tile = pt.pauli.tile;
   s.pauli_wg = pt.pauli.n_wg;
+  s.tune_ms = pt.tune_ms;
   *out = s;
 }
 

@@ -75,6 +75,7 @@ class q2c_stats(C.Structure):
         ("graph_launches", C.c_int),
         ("pauli_tile", C.c_int),
         ("pauli_wg", C.c_int),
+        ("tune_ms", C.c_double),
     ]
 
     PHASES = ("contract", "reduce", "values", "vectors", "back", "update")

@@ -3,6 +3,7 @@ import os
 import sys
 
 import numpy as np
+import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
@@ -22,3 +23,21 @@ def test_gate_flops_formula():
     # 128 x 128 saturated gate: contraction 32*64^3 + 128*64^2, SVD 4(4 m n^2 + 8 n^3), update 8*128*128*64
     f = bench.gate_flops(64, 64, 64, 64)
     assert f == 32 * 64 ** 3 + 128 * 64 ** 2 + 4 * (4 * 128 ** 3 + 8 * 128 ** 3) + 8 * 128 * 128 * 64
+
+
+def test_forked_gate_fraction():
+    """Fork-schedule work fraction: with one rotation per batch it is the
+    mean over rotations of the gates left after each fork gate; with a
+    single batch, the gates left after the earliest fork gate."""
+    q2c = pytest.importorskip("paper_2207_03711_amd.q2c", reason="libq2c.so not built")
+    from workloads import CONFIGS
+
+    I = CONFIGS["q8_d16"].integrals()
+    p = q2c.Problem(None, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+    _, rot, _, _ = q2c.vqe_problem_gates(p.h)
+    n = len(rot)
+    fork = np.array([np.flatnonzero(rot == m)[0] for m in range(p.info["n_rotations"])])
+    assert np.all(np.diff(fork) > 0)
+    assert abs(bench.forked_gate_fraction(p, 2) - np.mean(n - fork) / n) < 1e-12
+    assert abs(bench.forked_gate_fraction(p, 10**6) - (n - fork.min()) / n) < 1e-12
+    p.close()
