@@ -206,6 +206,100 @@ __device__ void bgemm(int M, int N, int K, const T* __restrict__ A, int lda, con
   __syncthreads();
 }
 
+// ---------------------------------------------------- MFMA complex GEMM --
+// C[M x N] = alpha * op(A) * op(B) (+ C if accumulate) on the matrix cores,
+// operands as in bgemm, read straight from memory (L2/L1-resident slot
+// workspace).  Each wave computes 16 x 16 NT strips of C, strips dealt out
+// round-robin over the waves; K advances 4 at a time (one 16x16x4 MFMA per
+// real product: Re += ar br - ai bi, Im += ar bi + ai br) with the next
+// operands loaded while the current ones multiply.  FP64 operands use
+// v_mfma_f64_16x16x4 (output row of lane l, register r: l / 16 + 4 r), FP32
+// operands v_mfma_f32_16x16x4 (output row 4 (l / 16) + r).  All threads of
+// the block must call it; it begins and ends with a block barrier.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaOps;
+template <>
+struct MfmaOps<double2> {
+  using R = double;
+  using Acc = mfma_d4;
+  static __device__ __forceinline__ Acc mma(R a, R b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MfmaOps<float2> {
+  using R = float;
+  using Acc = mfma_f4;
+  static __device__ __forceinline__ Acc mma(R a, R b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <bool TA, bool TB, typename T, int NT>
+__device__ __noinline__ void zgemm_mfma(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restrict__ B,
+                                        int ldb, T* __restrict__ C, int ldc, T alpha, bool accumulate) {
+  using Op = MfmaOps<T>;
+  using Acc = typename Op::Acc;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 16 * NT - 1) / (16 * NT);
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * (16 * NT);
+    const int ia = i0 + li;
+    auto ldA = [&](int k) -> T {
+      if (ia >= M || k >= K) return cval<T>(0.0, 0.0);
+      return TA ? cconj(A[(long)k * lda + ia]) : A[(long)ia * lda + k];
+    };
+    auto ldB = [&](int k, int j) -> T {
+      if (j >= N || k >= K) return cval<T>(0.0, 0.0);
+      return TB ? cconj(B[(long)j * ldb + k]) : B[(long)k * ldb + j];
+    };
+    Acc cr[NT], ci[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      cr[q] = Acc{0, 0, 0, 0};
+      ci[q] = Acc{0, 0, 0, 0};
+    }
+    T a = ldA(lk), bb[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) bb[q] = ldB(lk, j0 + 16 * q + li);
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kn = k0 + 4 + lk;
+      const T an = ldA(kn);
+      T bn[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) bn[q] = ldB(kn, j0 + 16 * q + li);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        cr[q] = Op::mma(a.x, bb[q].x, cr[q]);
+        cr[q] = Op::mma(-a.y, bb[q].y, cr[q]);
+        ci[q] = Op::mma(a.x, bb[q].y, ci[q]);
+        ci[q] = Op::mma(a.y, bb[q].x, ci[q]);
+      }
+      a = an;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) bb[q] = bn[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + Op::row(lk, r), col = j0 + 16 * q + li;
+        if (row < M && col < N) {
+          T v;
+          v.x = cr[q][r];
+          v.y = ci[q][r];
+          v = cmul(alpha, v);
+          T* dst = &C[(long)row * ldc + col];
+          *dst = accumulate ? cadd(*dst, v) : v;
+        }
+      }
+  }
+  __syncthreads();
+}
+
 // Householder vector for a row (conj=true: reflector applied from the
 // right to rows, built from conj(x)) or a column (conj=false).
 // Given x (len L) returns u with H = I - u u^H mapping x -> -ph*|x| e_0 and
@@ -533,8 +627,8 @@ __device__ void gate_contract(const DevBatch& b, SlotView& v, GateLds& L, int n,
   const S* Bn1 = sites + b.site_off[n + 1];
   S* Mw = reinterpret_cast<S*>(v.M);
   for (int j = 0; j < 2; ++j)
-    bgemm<false, false, S>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, Mw + j * chir, nn,
-                           cval<S>(1.0, 0.0), false, reinterpret_cast<S*>(L.gemm));
+    zgemm_mfma<false, false, S, 4>(m, chir, chim, Bn, capl_r, Bn1 + j * capr_r, 2 * capr_r, Mw + j * chir, nn,
+                                   cval<S>(1.0, 0.0), false);
   double part = 0.0;
   for (int idx = tid; idx < chil * chir; idx += blockDim.x) {
     const int a = idx / chir, c = idx - a * chir;
@@ -1612,15 +1706,15 @@ __global__ __launch_bounds__(kBlock) void k_gates(DevBatch b, const int* __restr
     __syncthreads();
     // B_n = M W / ||S_kept||  (Eq. 10: no division by Schmidt values)
     if constexpr (sizeof(S) == sizeof(double2)) {
-      bgemm<false, true, S>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, reinterpret_cast<const S*>(v.W), nn, Bn,
-                            capl_r, cval<S>(1.0 / nrm, 0.0), false, reinterpret_cast<S*>(L.gemm));
+      zgemm_mfma<false, true, S, 4>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, reinterpret_cast<const S*>(v.W),
+                                    nn, Bn, capl_r, cval<S>(1.0 / nrm, 0.0), false);
     } else {
       // mixed path: the kept rows of W^H rounded to complex64 (reflector scratch), then M W in FP32
       S* Wf = reinterpret_cast<S*>(v.H);
       for (int idx = tid; idx < keep * nn; idx += blockDim.x) Wf[idx] = cfrom<S>(v.W[idx]);
       __syncthreads();
-      bgemm<false, true, S>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, Wf, nn, Bn, capl_r,
-                            cval<S>(1.0 / nrm, 0.0), false, reinterpret_cast<S*>(L.gemm));
+      zgemm_mfma<false, true, S, 4>(m, keep, nn, reinterpret_cast<const S*>(v.M), nn, Wf, nn, Bn, capl_r,
+                                    cval<S>(1.0 / nrm, 0.0), false);
     }
     if (tid == 0) {
       v.chi[n + 1] = keep;
