@@ -454,9 +454,8 @@ struct GateLds {
       double2 uq[512], wq[512], vq[512], zq[512];  // Jacobi-path work vectors
     };
     struct {
-      double2 col[kQB], row[kQB], w[kQB];
+      double2 rowb[2][kQB], w[kQB];
       double2 part[8][kQB];
-      double nrm[8], rnrm;
     } bd;                      // exchange area of the bidiagonalisation
     double Z[2 * kQB * kZS];   // twisted factorisations, kept vectors, Gram; later reflectors
   };
@@ -584,6 +583,14 @@ __device__ __forceinline__ void cfms(double2& x, double2 a, double2 b) {
   x.y = fma(-a.x, b.y, x.y);
   x.y = fma(-a.y, b.x, x.y);
 }
+// y - conj(a) b
+__device__ __forceinline__ double2 cfms_conj_val(double2 y, double2 a, double2 b) {
+  y.x = fma(-a.x, b.x, y.x);
+  y.x = fma(-a.y, b.y, y.x);
+  y.y = fma(-a.x, b.y, y.y);
+  y.y = fma(a.y, b.x, y.y);
+  return y;
+}
 __device__ __forceinline__ void cfms_conj(double2& x, double2 a, double2 b) {
   x.x = fma(-a.x, b.x, x.x);
   x.x = fma(-a.y, b.y, x.x);
@@ -690,43 +697,23 @@ template <int KS>
 __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const BdArgs& a, GateLds& L) {
   constexpr int RSK = KS / 2, CSK = KS;
   const int tid = threadIdx.x;
-  // ---- H_k on column k, rows k .. p-1
+  double2* rowb = L.bd.rowb[k & 1];  // row k before H_k (double-buffered: a wave may run one step ahead)
+  // ---- A: x = column k (rows k .. p-1) from the lane that holds it in this
+  // thread's 16-lane row group; partial y_j = sum_i conj(x_i) X_ij over this
+  // thread's rows (y_k = |x|^2), reduced over the four lanes sharing c0.
+  double2 x[4];
   {
-    const bool own = a.c0 == (k & 15);
-    double s = 0.0;
-#pragma unroll
-    for (int rs = RSK; rs < 4; ++rs) {
-      const int i = a.r0 + 32 * rs;
-      const double2 xv = i >= k ? X[rs][CSK] : cmk(0.0, 0.0);
-      if (own) L.bd.col[i] = xv;
-      s += cabs2(xv);
-    }
-    s = own ? s : 0.0;
-    s = pair_sum16(s, s);
-    s = pair_sum32(s, s);
-    if (own && a.lane < 16) L.bd.nrm[a.wave] = s;
-  }
-  __syncthreads();
-  double2 u[4];
-  bool zero;
-  {
-    double n2 = 0.0;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) n2 += L.bd.nrm[w];
-    const HhScalars h = hh_scalars(n2, L.bd.col[k]);
-    zero = h.zero;
-    if (tid == 0) L.dc[k] = h.beta;
+    const int src = (a.lane & 0x30) | (k & 15);
 #pragma unroll
     for (int rs = 0; rs < 4; ++rs) {
-      const int i = a.r0 + 32 * rs;
-      double2 uv = cmk(0.0, 0.0);
-      if (rs >= RSK && i >= k && !zero) uv = i == k ? cscale(h.ph, h.head) : cscale(L.bd.col[i], h.inv);
-      u[rs] = uv;
-      if (a.trans && a.c0 == 0 && rs >= RSK && i >= k && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
+      double2 xv = cmk(0.0, 0.0);
+      if (rs >= RSK) {
+        xv.x = __shfl(X[rs][CSK].x, src, 64);
+        xv.y = __shfl(X[rs][CSK].y, src, 64);
+        if (a.r0 + 32 * rs < k) xv = cmk(0.0, 0.0);
+      }
+      x[rs] = xv;
     }
-  }
-  if (!zero) {
-    // partial w_j = sum_i conj(u_i) X_ij over this thread's rows
     double2 wp[8];
 #pragma unroll
     for (int cs = 0; cs < 8; ++cs) {
@@ -734,11 +721,11 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
       if (cs >= CSK) {
 #pragma unroll
         for (int rs = RSK; rs < 4; ++rs) {
-          const double2 uc = u[rs], x = X[rs][cs];
-          acc.x = fma(uc.x, x.x, acc.x);
-          acc.x = fma(uc.y, x.y, acc.x);
-          acc.y = fma(uc.x, x.y, acc.y);
-          acc.y = fma(-uc.y, x.x, acc.y);
+          const double2 uc = x[rs], xv = X[rs][cs];
+          acc.x = fma(uc.x, xv.x, acc.x);
+          acc.x = fma(uc.y, xv.y, acc.x);
+          acc.y = fma(uc.x, xv.y, acc.y);
+          acc.y = fma(-uc.y, xv.x, acc.y);
         }
       }
       wp[cs] = acc;
@@ -753,56 +740,91 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
     const int sb = 4 * ((a.lane >> 5) & 1) + 2 * ((a.lane >> 4) & 1);
     L.bd.part[a.wave][a.c0 + 16 * sb] = g[0];
     L.bd.part[a.wave][a.c0 + 16 * (sb + 1)] = g[1];
-  }
-  __syncthreads();
-  if (!zero && tid < kQB) {
-    double2 s = cmk(0.0, 0.0);
-    if (tid > k) {
+    if (a.r0 == (k & 31)) {
 #pragma unroll
-      for (int w = 0; w < 8; ++w) s = cadd(s, L.bd.part[w][tid]);
+      for (int cs = CSK; cs < 8; ++cs) rowb[a.c0 + 16 * cs] = X[RSK][cs];
     }
-    L.bd.w[tid] = s;
   }
   __syncthreads();
-  if (!zero) {
+  // ---- B: y_j = sum over the waves (j >= k)
+  if (tid < kQB) {
+    double2 sy = cmk(0.0, 0.0);
+    if (tid >= k) {
 #pragma unroll
-    for (int cs = CSK; cs < 8; ++cs) {
-      const double2 wj = L.bd.w[a.c0 + 16 * cs];
+      for (int w = 0; w < 8; ++w) sy = cadd(sy, L.bd.part[w][tid]);
+    }
+    L.bd.w[tid] = sy;
+  }
+  __syncthreads();
+  // ---- C: H_k = I - u u^H from |x|^2 = Re y_k and the pivot X_kk; with
+  // u = inv (x - alpha e_k), w_j = sum_i conj(u_i) X_ij = inv (y_j - conj(alpha) X_kj)
+  const HhScalars h = hh_scalars(L.bd.w[k].x, rowb[k]);
+  if (tid == 0) L.dc[k] = h.beta;
+  const double2 uk = cscale(h.ph, h.head);
+  double2 wj[8], rj[8];  // w_j and row k before H_k, own columns (zero for j <= k)
 #pragma unroll
-      for (int rs = RSK; rs < 4; ++rs) cfms(X[rs][cs], u[rs], wj);
+  for (int cs = 0; cs < 8; ++cs) {
+    const int j = a.c0 + 16 * cs;
+    double2 wv = cmk(0.0, 0.0), rv = cmk(0.0, 0.0);
+    if (cs >= CSK && j > k) {
+      rv = rowb[j];
+      if (!h.zero) {
+        const double2 yv = L.bd.w[j];
+        wv = cscale(cfms_conj_val(yv, h.beta, rv), h.inv);
+      }
+    }
+    wj[cs] = wv;
+    rj[cs] = rv;
+  }
+  {
+    // u (zero when the column is already zero: H_k = I, stored as such)
+    double2 u[4];
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs) {
+      const int i = a.r0 + 32 * rs;
+      double2 uv = cmk(0.0, 0.0);
+      if (rs >= RSK && i >= k && !h.zero) uv = i == k ? uk : cscale(x[rs], h.inv);
+      u[rs] = uv;
+      if (a.trans && a.c0 == 0 && rs >= RSK && i >= k && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
+    }
+    if (!h.zero) {
+#pragma unroll
+      for (int cs = CSK; cs < 8; ++cs)
+#pragma unroll
+        for (int rs = RSK; rs < 4; ++rs) cfms(X[rs][cs], u[rs], wj[cs]);
     }
   }
   if (k >= a.q - 1) return;
-  // ---- G_k on row k, columns k+1 .. q-1
-  {
-    const bool own = a.r0 == (k & 31);
-    double s = 0.0;
-    if (own) {
+  // ---- G_k on row k after H_k, columns k+1 .. q-1: every 16-lane row group
+  // rebuilds the row from rowb and w (the owner's registers hold the same
+  // values) and sums its norm, so no exchange is needed.
+  double s = 0.0;
 #pragma unroll
-      for (int cs = CSK; cs < 8; ++cs) {
-        const int j = a.c0 + 16 * cs;
-        const double2 xv = j > k ? X[RSK][cs] : cmk(0.0, 0.0);
-        L.bd.row[j] = xv;
-        s += cabs2(xv);
-      }
-    }
-    s = row16_sum(s);
-    if (own && a.c0 == 0) L.bd.rnrm = s;
+  for (int cs = 0; cs < 8; ++cs) {
+    double2 r = rj[cs];
+    if (!h.zero) cfms(r, uk, wj[cs]);
+    rj[cs] = r;
+    s += cabs2(r);
   }
-  __syncthreads();
-  const HhScalars h = hh_scalars(L.bd.rnrm, L.bd.row[k + 1]);
-  const bool rzero = h.zero;
-  if (tid == 0) L.ec[k] = h.beta;
+  s = row16_sum(s);
+  double2 rk1 = cmk(0.0, 0.0);
+  if (k + 1 < a.q) {
+    rk1 = rowb[k + 1];
+    if (!h.zero) cfms(rk1, uk, cscale(cfms_conj_val(L.bd.w[k + 1], h.beta, rk1), h.inv));
+  }
+  const HhScalars g = hh_scalars(s, rk1);
+  if (tid == 0) L.ec[k] = g.beta;
+  // v (zero when the row is already zero: G_k = I, stored as such)
   double2 vv[8];
 #pragma unroll
   for (int cs = 0; cs < 8; ++cs) {
     const int j = a.c0 + 16 * cs;
-    double2 x = cmk(0.0, 0.0);
-    if (cs >= CSK && j > k && !rzero) x = cconj(j == k + 1 ? cscale(h.ph, h.head) : cscale(L.bd.row[j], h.inv));
-    vv[cs] = x;
-    if (!a.trans && a.r0 == 0 && cs >= CSK && j > k && j < a.q) a.Hg[(long)k * a.ldh + j] = x;
+    double2 xv = cmk(0.0, 0.0);
+    if (cs >= CSK && j > k && !g.zero) xv = cconj(j == k + 1 ? cscale(g.ph, g.head) : cscale(rj[cs], g.inv));
+    vv[cs] = xv;
+    if (!a.trans && a.r0 == 0 && cs >= CSK && j > k && j < a.q) a.Hg[(long)k * a.ldh + j] = xv;
   }
-  if (rzero) return;
+  if (g.zero) return;
   // z_i = sum_j X_ij v_j; rows are whole within a 16-lane row of the wave
   double2 zp[4];
 #pragma unroll
@@ -1039,6 +1061,62 @@ __device__ __noinline__ void svd_values(GateLds& L, const SvdShape& sh) {
 // Step 3: orthonormal real vectors of the bidiagonal for the kept values in
 // rows 2k + off of L.Z (off = 1 when X = M'^H).  Unscales L.sig.  Returns
 // false if the vectors could not be certified.
+// One Cholesky QR pass on the q x keep columns Y (row k at Yb + 2 k kZS) with
+// the summed Gram matrix in Gb2: G = L L^T (lower triangle), reciprocal
+// diagonal in L.ldiag, then Y <- Y L^{-T}.  False if G is not numerically
+// positive definite.  A separate function: its register use stays out of the
+// common path of svd_vectors.
+__device__ __noinline__ bool vec_cholqr(GateLds& L, double* Yb, double* Gb2, int q, int keep) {
+  const int tid = threadIdx.x;
+  q = uni(q);
+  keep = uni(keep);
+  for (int jj = 0; jj < keep; ++jj) {
+    const double djj = Gb2[(long)(2 * jj) * kZS + jj];
+    if (!(djj > 1e-10) || !isfinite(djj)) return false;  // the same value in every thread
+    const double rinv = 1.0 / sqrt(djj);
+    for (int ra = jj + 1 + tid; ra < keep; ra += blockDim.x) Gb2[(long)(2 * ra) * kZS + jj] *= rinv;
+    if (tid == 0) L.ldiag[jj] = rinv;
+    __syncthreads();
+    const int rem = keep - jj - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int ra = jj + 1 + e / rem, rc = jj + 1 + e % rem;
+      if (rc <= ra) Gb2[(long)(2 * ra) * kZS + rc] -= Gb2[(long)(2 * ra) * kZS + jj] * Gb2[(long)(2 * rc) * kZS + jj];
+    }
+    __syncthreads();
+  }
+  {
+    // row k of Y solves L x = y; thread (k, s4) holds entries s4 + 4 t
+    const int k = tid >> 2, s4 = tid & 3;
+    double* yr = Yb + (long)(2 * k) * kZS;
+    double y[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = s4 + 4 * t;
+      y[t] = (k < q && e < keep) ? yr[e] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kKB; ++c) {
+      if (c < keep) {
+        double part = 0.0;
+#pragma unroll
+        for (int t = 0; t < (c + 3) / 4; ++t) {
+          const int e = 4 * t + s4;
+          if (e < c) part = fma(y[t], Gb2[(long)(2 * c) * kZS + e], part);
+        }
+        part = quad_sum(part);
+        if (s4 == (c & 3)) y[c >> 2] = (y[c >> 2] - part) * L.ldiag[c];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = s4 + 4 * t;
+      if (k < q && e < keep) yr[e] = y[t];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 __device__ __noinline__ bool svd_vectors(GateLds& L, const SvdShape& sh, int keep) {
   keep = uni(keep);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1240,154 +1318,180 @@ __device__ __noinline__ bool svd_vectors(GateLds& L, const SvdShape& sh, int kee
       if (err * keep <= 1e-7) break;
       continue;
     }
-    // Cholesky QR: G = L L^T (lower triangle of the summed Gram matrix, in Gb2),
-    // reciprocal diagonal in ldiag, then Y <- Y L^{-T}
-    for (int jj = 0; jj < keep; ++jj) {
-      const double djj = Gb2[(long)(2 * jj) * kZS + jj];
-      if (!(djj > 1e-10) || !isfinite(djj)) return false;  // the same value in every thread
-      const double rinv = 1.0 / sqrt(djj);
-      for (int ra = jj + 1 + tid; ra < keep; ra += blockDim.x) Gb2[(long)(2 * ra) * kZS + jj] *= rinv;
-      if (tid == 0) L.ldiag[jj] = rinv;
-      __syncthreads();
-      const int rem = keep - jj - 1;
-      for (int e = tid; e < rem * rem; e += blockDim.x) {
-        const int ra = jj + 1 + e / rem, rc = jj + 1 + e % rem;
-        if (rc <= ra) Gb2[(long)(2 * ra) * kZS + rc] -= Gb2[(long)(2 * ra) * kZS + jj] * Gb2[(long)(2 * rc) * kZS + jj];
-      }
-      __syncthreads();
-    }
-    {
-      // row k of Y solves L x = y; thread (k, s4) holds entries s4 + 4 t
-      const int k = tid >> 2, s4 = tid & 3;
-      double* yr = Yb + (long)(2 * k) * kZS;
-      double y[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int e = s4 + 4 * t;
-        y[t] = (k < q && e < keep) ? yr[e] : 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < kKB; ++c) {
-        if (c < keep) {
-          double part = 0.0;
-#pragma unroll
-          for (int t = 0; t < (c + 3) / 4; ++t) {
-            const int e = 4 * t + s4;
-            if (e < c) part = fma(y[t], Gb2[(long)(2 * c) * kZS + e], part);
-          }
-          part = quad_sum(part);
-          if (s4 == (c & 3)) y[c >> 2] = (y[c >> 2] - part) * L.ldiag[c];
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int e = s4 + 4 * t;
-        if (k < q && e < keep) yr[e] = y[t];
-      }
-    }
+    if (!vec_cholqr(L, Yb, Gb2, q, keep)) return false;
     __syncthreads();
   }
   return true;
 }
 
-// Step 4: kept rows of W^H into v.W (keep x nn).
+// Step 4: kept rows of W^H into v.W (keep x nn).  W (nn x keep, complex) =
+// the bidiagonal's vectors times the phases, then through the reflectors in
+// blocks of 16 (compact WY, reflectors H = I - u u^H with |u|^2 = 2, tau = 1):
+// H_k1 H_k1+1 ... H_k1+15 = I - V T V^H, T upper triangular with unit
+// diagonal, T(0:c, c) = -T(0:c, 0:c) (V^H V)(0:c, c); W <- W - V (T (V^H W)).
+// The products run on FP64 MFMA 16x16x4.  W stays in registers in the MFMA
+// output layout: wave w holds columns 16 (w % 4) .. + 15 and rows
+// 64 (w / 4) .. + 63 as four 16 x 16 tiles, lane l and register r of tile t
+// holding row 64 (w / 4) + 16 t + l / 16 + 4 r, column 16 (w % 4) + l % 16.
+// That is the layout of the B operand of a 16x16x4 product whose k-block is
+// the tile's rows 4 r .. 4 r + 3, so V^H W and V Z take W and Z straight
+// from registers.  Reflector k (row k of v.H, stride ws) is read from the
+// workspace and masked to its support [st_k, st_k + len_k).
 __device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdShape& sh, int keep) {
+  using Op = MfmaOps<double2>;
+  using Acc = mfma_d4;
   keep = uni(keep);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int p = uni(sh.p), q = uni(sh.q), nn = uni(sh.nn);
   const bool trans = p != uni(sh.m);
-  (void)tid; (void)lane; (void)wave; (void)trans; (void)p; (void)q; (void)nn;
   const int ws = uni(sh.ws);
-  double2* Hg = v.H;
+  const double2* Hg = v.H;
   const int off = trans ? 1 : 0;
-  double* Yb = L.Z + off * kZS;
-  // -- complex vectors of the bidiagonal, then through the reflectors, held in
-  // registers: thread (vl, pl) = (lane / 16, lane % 16) of wave w holds vectors
-  // j = 8 w + 2 vl + s (s < 2) at positions pl + 16 e (e < 8)
+  const double* Yb = L.Z + off * kZS;
+  const int ct = wave & 3, rh = wave >> 2;
+  const int li = lane & 15, lk = lane >> 4;
+  const int kstart = trans ? q - 1 : q - 2;  // last reflector
+  // reflector k: support start and length (zero beyond kstart)
+  auto refl = [&](int k, int i) -> double2 {
+    if (k > kstart) return cmk(0.0, 0.0);
+    const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
+    return (i >= st && i < st + len) ? Hg[(long)k * ws + i] : cmk(0.0, 0.0);
+  };
+  // -- W = phases * bidiagonal vectors
+  Acc wre[4], wim[4];
   {
-    const int vl = lane >> 4, pl = lane & 15;
     const double2* phase = trans ? L.pa : L.pb;
-    double2 Wr[2][8];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = 8 * wave + 2 * vl + s, pos = pl + 16 * e;
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 64 * rh + 16 * t + lk + 4 * r, j = 16 * ct + li;
         double2 x = cmk(0.0, 0.0);
         if (j < keep && pos < q) x = cscale(phase[pos], Yb[(long)(2 * pos) * kZS + j]);
-        Wr[s][e] = x;
-      }
-    __syncthreads();
-    // stage the reflectors in LDS, packed: reflector k has len_k entries from st_k
-    double2* R = reinterpret_cast<double2*>(L.Z);
-    const int kstart = trans ? q - 1 : q - 2;
-    for (int k0 = wave; k0 <= kstart; k0 += 64) {
-      // up to 8 reflectors per wave in flight: issue every load, then write
-      double2 buf[8][2];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int k = k0 + 8 * r;
-        const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int i = lane + 64 * h;
-          buf[r][h] = (k <= kstart && i < len) ? Hg[(long)k * ws + st + i] : cmk(0.0, 0.0);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int k = k0 + 8 * r;
-        const int len = trans ? p - k : q - k - 1;
-        const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int i = lane + 64 * h;
-          if (k <= kstart && i < len) R[ro + i] = buf[r][h];
-        }
-      }
-    }
-    __syncthreads();
-    for (int k = kstart; k >= 0; --k) {
-      const int st = trans ? k : k + 1, len = trans ? p - k : q - k - 1;
-      const int ro = trans ? k * p - k * (k - 1) / 2 : k * (q - 1) - k * (k - 1) / 2;
-      double2 u[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int pos = pl + 16 * e;
-        u[e] = (pos >= st && pos < st + len) ? R[ro + pos - st] : cmk(0.0, 0.0);
-      }
-      double2 d[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (16 * e + 15 < st || 16 * e >= st + len) continue;  // the same for all lanes
-          const double2 uc = u[e], x = Wr[s][e];
-          ar = fma(uc.x, x.x, ar);
-          br = fma(uc.y, x.y, br);
-          ai = fma(uc.x, x.y, ai);
-          bi = fma(-uc.y, x.x, bi);
-        }
-        d[s] = cmk(row16_sum(ar + br), row16_sum(ai + bi));
-      }
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (16 * e + 15 < st || 16 * e >= st + len) continue;
-          cfms(Wr[s][e], u[e], d[s]);
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = 8 * wave + 2 * vl + s, pos = pl + 16 * e;
-        if (j < keep && pos < nn) v.W[(long)j * nn + pos] = cconj(Wr[s][e]);  // rows of W^H
+        wre[t][r] = x.x;
+        wim[t][r] = x.y;
       }
   }
-  __syncthreads();
+  __syncthreads();  // Yb is read; L.Z becomes scratch
+  double2* Tb = reinterpret_cast<double2*>(L.Z);  // [8][16][16]: T of block b (reflectors 16 b ..)
+  double2* Vb = Tb + 8 * 256;                     // [2][16][128]: V of a block, V(i, n) at n * 128 + i
+  double2* Sp = Vb + 2 * 16 * 128;                // [2][16][64]: partial V^H W by row half
+  if (kstart < 0) goto store;
+  {
+    const int nblk = kstart / 16 + 1;  // <= 8
+    // -- T of every block, wave w for block w: G = V^H V on MFMA (rows from the
+    // block's first support row), then row n of T in lane n:
+    // T(n, c) = -sum_{n <= m < c} T(n, m) G(m, c)
+    if (wave < nblk) {
+      const int k1 = 16 * wave, st1 = trans ? k1 : k1 + 1;
+      Acc gr = Acc{0, 0, 0, 0}, gi = Acc{0, 0, 0, 0};
+      for (int i0 = (st1 / 4) * 4; i0 < p; i0 += 4) {
+        const double2 u = refl(k1 + li, i0 + lk);  // A = conj(V)(li, i), B = V(i, li): the same element
+        gr = Op::mma(u.x, u.x, gr);
+        gr = Op::mma(u.y, u.y, gr);   // Re conj(a) b = ar br + ai bi
+        gi = Op::mma(u.x, u.y, gi);
+        gi = Op::mma(-u.y, u.x, gi);  // Im conj(a) b = ar bi - ai br
+      }
+      double2* Tw = Tb + wave * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tw[(lk + 4 * r) * 16 + li] = cmk(gr[r], gi[r]);  // G for now
+      wave_sync();
+      double2 trow[16];
+      const int n = li;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double2 acc = cmk(0.0, 0.0);
+#pragma unroll
+        for (int m = 0; m < c; ++m)
+          if (m >= n) cfma(acc, trow[m], Tw[m * 16 + c]);
+        trow[c] = c < n ? cmk(0.0, 0.0) : (c == n ? cmk(1.0, 0.0) : cmk(-acc.x, -acc.y));
+      }
+      wave_sync();
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Tw[n * 16 + c] = trow[c];
+      }
+    }
+    // -- V of block b goes to Vb[b & 1]; each thread stages 4 entries per block
+    auto vload = [&](int k1, double2 (&nv)[4]) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = tid + 512 * e, n = idx >> 7, i = idx & 127;
+        nv[e] = refl(k1 + n, i);
+      }
+    };
+    double2 nv[4];
+    vload(16 * (nblk - 1), nv);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Vb[((nblk - 1) & 1) * 2048 + tid + 512 * e] = nv[e];
+    for (int b = nblk - 1; b >= 0; --b) {
+      const int k1 = 16 * b, st1 = trans ? k1 : k1 + 1;
+      const double2* V = Vb + (b & 1) * 2048;
+      const double2* T = Tb + b * 256;
+      __syncthreads();  // V of this block (and every T) staged; the previous block's Sp reads are done
+      if (b > 0) vload(k1 - 16, nv);  // next block's V, in flight during this one
+      // -- partial S = V^H W over this wave's rows, for its 16 columns
+      {
+        Acc sr = Acc{0, 0, 0, 0}, si = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (64 * rh + 16 * t + 15 < st1) continue;  // the same for the whole wave
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 64 * rh + 16 * t + 4 * r + lk;
+            const double2 u = V[li * 128 + i];  // A(li, i) = conj(V(i, li))
+            sr = Op::mma(u.x, wre[t][r], sr);
+            sr = Op::mma(u.y, wim[t][r], sr);   // Re conj(u) w = ur wr + ui wi
+            si = Op::mma(u.x, wim[t][r], si);
+            si = Op::mma(-u.y, wre[t][r], si);  // Im conj(u) w = ur wi - ui wr
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Sp[rh * 1024 + (lk + 4 * r) * 64 + 16 * ct + li] = cmk(sr[r], si[r]);
+      }
+      __syncthreads();
+      // -- Z = T S for this wave's columns (both row halves compute it), then W -= V Z
+      {
+        Acc zr = Acc{0, 0, 0, 0}, zi = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int m = 4 * s4 + lk;
+          const double2 a = T[li * 16 + m];
+          const double2 bs = cadd(Sp[m * 64 + 16 * ct + li], Sp[1024 + m * 64 + 16 * ct + li]);
+          zr = Op::mma(a.x, bs.x, zr);
+          zr = Op::mma(-a.y, bs.y, zr);
+          zi = Op::mma(a.x, bs.y, zi);
+          zi = Op::mma(a.y, bs.x, zi);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (64 * rh + 16 * t + 15 < st1) continue;
+          const int i = 64 * rh + 16 * t + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double2 u = V[(4 * r + lk) * 128 + i];  // A(i, n) = -V(i, n), n = 4 r + lk; B = Z register r
+            wre[t] = Op::mma(-u.x, zr[r], wre[t]);
+            wre[t] = Op::mma(u.y, zi[r], wre[t]);
+            wim[t] = Op::mma(-u.x, zi[r], wim[t]);
+            wim[t] = Op::mma(-u.y, zr[r], wim[t]);
+          }
+        }
+      }
+      if (b > 0) {
+        double2* Vn = Vb + ((b - 1) & 1) * 2048;  // last read two blocks ago
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Vn[tid + 512 * e] = nv[e];
+      }
+    }
+  }
+store:
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 64 * rh + 16 * t + lk + 4 * r, j = 16 * ct + li;
+      if (j < keep && pos < nn) v.W[(long)j * nn + pos] = cmk(wre[t][r], -wim[t][r]);  // rows of W^H
+    }
   __syncthreads();
 }
 
