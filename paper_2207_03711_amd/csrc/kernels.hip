@@ -525,10 +525,14 @@ __device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
   unsigned last = (unsigned)__double2hiint(pc) >> 31;  // sign bit of p_1
   int c = (int)last;                                   // p_0 = 1 > 0
   int i = 1;
-  for (; i + 8 <= n; i += 8) {
-    double tt[8];
+  // t2 is read one chunk of eight ahead (t2 has 8 entries of padding past n - 1)
+  double tt[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) tt[u] = t2[i - 1 + u];
+  for (int u = 0; u < 8; ++u) tt[u] = t2[u];
+  for (; i + 8 <= n; i += 8) {
+    double tn[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tn[u] = t2[i + 7 + u];
     // shift register of sign bits: bit 8 holds the sign of p_i, bit 0 that of p_{i+8}
     unsigned w = last;
 #pragma unroll
@@ -545,6 +549,8 @@ __device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
       pc = ldexp(pc, -e);
       pm = ldexp(pm, -e);
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tt[u] = tn[u];
   }
   for (; i < n; ++i) {
     const double pn = fma(nx, pc, -t2[i - 1] * pm);
