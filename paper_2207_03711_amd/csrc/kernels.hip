@@ -440,7 +440,7 @@ constexpr int kZS = kKB + 1;  // row stride (doubles) of the vector work array
 struct GateLds {
   double2 O[16];
   double2 dc[kQB], ec[kQB], pa[kQB], pb[kQB];  // bidiagonal and its phases
-  double t[2 * kQB], t2[2 * kQB + 8];          // Golub-Kahan tridiagonal (t2 zero-padded)
+  double t[2 * kQB], t2[2 * kQB + 16];         // Golub-Kahan tridiagonal (t2 zero-padded)
   double sig[512];                             // kept singular values, descending
   double ldiag[kKB];                           // reciprocal Cholesky diagonal
   int blo[2 * kQB], bhi[2 * kQB];              // blocks of the split tridiagonal
@@ -516,41 +516,44 @@ __device__ __forceinline__ double wave_max(double v) {
 // whose squared off-diagonals are t2[0 .. n-2]: the sign changes along the
 // leading minors p_0 = 1, p_1 = -x, p_{i+1} = -x p_i - t2[i-1] p_{i-1}.  A zero
 // off-diagonal needs no special case (minors of a block-diagonal matrix
-// factorise).  With |t| <= 1 and 0 < x <= 1 the values grow by less than 2^6
-// over eight steps, so a power-of-two renormalisation every eight steps keeps
-// them in range.  Division-free.
+// factorise).  With |t| <= 1 and 0 < x <= 1 the values grow by less than 2^12
+// over sixteen steps; off-diagonals below 1e-15 of the largest are split off,
+// so t2 >= 1e-30 and a pair of minors shrinks by at most 2^-800 over sixteen
+// steps.  A power-of-two renormalisation whenever the larger exponent leaves
+// [-200, 200], checked every sixteen steps, keeps them in range.
+// Division-free.  t2 must be readable up to index n + 14 (zero padding).
 __device__ int sturm_count(const double* __restrict__ t2, int n, double x) {
   const double nx = -x;
   double pm = 1.0, pc = nx;
   unsigned last = (unsigned)__double2hiint(pc) >> 31;  // sign bit of p_1
   int c = (int)last;                                   // p_0 = 1 > 0
   int i = 1;
-  // t2 is read one chunk of eight ahead (t2 has 8 entries of padding past n - 1)
-  double tt[8];
+  // t2 is read one chunk of sixteen ahead
+  double tt[16];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) tt[u] = t2[u];
-  for (; i + 8 <= n; i += 8) {
-    double tn[8];
+  for (int u = 0; u < 16; ++u) tt[u] = t2[u];
+  for (; i + 16 <= n; i += 16) {
+    double tn[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) tn[u] = t2[i + 7 + u];
-    // shift register of sign bits: bit 8 holds the sign of p_i, bit 0 that of p_{i+8}
+    for (int u = 0; u < 16; ++u) tn[u] = t2[i + 15 + u];
+    // shift register of sign bits: bit 16 holds the sign of p_i, bit 0 that of p_{i+16}
     unsigned w = last;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const double pn = fma(nx, pc, -tt[u] * pm);
       pm = pc;
       pc = pn;
       w = __builtin_amdgcn_alignbit(w, (unsigned)__double2hiint(pn), 31u);
     }
-    c += __builtin_popcount((w ^ (w >> 1)) & 0xFFu);
+    c += __builtin_popcount((w ^ (w >> 1)) & 0xFFFFu);
     last = w & 1u;
     const int e = max(__builtin_amdgcn_frexp_exp(pc), __builtin_amdgcn_frexp_exp(pm));
-    if (e > 400 || e < -400) {
+    if (e > 200 || e < -200) {
       pc = ldexp(pc, -e);
       pm = ldexp(pm, -e);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) tt[u] = tn[u];
+    for (int u = 0; u < 16; ++u) tt[u] = tn[u];
   }
   for (; i < n; ++i) {
     const double pn = fma(nx, pc, -t2[i - 1] * pm);
@@ -988,7 +991,7 @@ __device__ __noinline__ void svd_values(GateLds& L, const SvdShape& sh) {
     gs = wave_max(gs);
     const double sc = gs > 0.0 ? 1.0 / gs : 1.0;
     wave_sync();
-    for (int i = lane; i < nT + 7; i += 64) {
+    for (int i = lane; i < nT + 15; i += 64) {
       const double x = i < nT - 1 ? L.t[i] * sc : 0.0;
       if (i < nT - 1) L.t[i] = x;
       L.t2[i] = x * x;
