@@ -686,6 +686,15 @@ __device__ void restore_mprime(const DevBatch& b, SlotView& v, int n, int chil, 
   __syncthreads();
 }
 
+// Values that are the same in every lane, moved to scalar registers so that
+// conditions on them compile to uniform branches (function arguments arrive in
+// vector registers and would otherwise count as divergent).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni(double x) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
 // ---- Phase B (default), step 1: Golub-Kahan bidiagonalisation of the p x q
 // matrix X (p >= q <= 128) held in registers.  Thread (r0, c0), r0 = 4 wave +
 // lane / 16, c0 = lane % 16, owns X[r0 + 32 rs][c0 + 16 cs] for rs < 4, cs < 8,
@@ -719,7 +728,8 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
       if (rs >= RSK) {
         xv.x = __shfl(X[rs][CSK].x, src, 64);
         xv.y = __shfl(X[rs][CSK].y, src, 64);
-        if (a.r0 + 32 * rs < k) xv = cmk(0.0, 0.0);
+        // rows in slots above RSK are all below row k; only slot RSK is masked
+        if (rs == RSK && a.r0 + 32 * rs < k) xv = cmk(0.0, 0.0);
       }
       x[rs] = xv;
     }
@@ -767,23 +777,26 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
   __syncthreads();
   // ---- C: H_k = I - u u^H from |x|^2 = Re y_k and the pivot X_kk; with
   // u = inv (x - alpha e_k), w_j = sum_i conj(u_i) X_ij = inv (y_j - conj(alpha) X_kj)
-  const HhScalars h = hh_scalars(L.bd.w[k].x, rowb[k]);
+  // every input of the reflector scalars is the same in all lanes; taken from
+  // lane 0 they are wave-uniform, so the branches on them are scalar
+  const HhScalars h = hh_scalars(uni(L.bd.w[k].x), cmk(uni(rowb[k].x), uni(rowb[k].y)));
   if (tid == 0) L.dc[k] = h.beta;
   const double2 uk = cscale(h.ph, h.head);
   double2 wj[8], rj[8];  // w_j and row k before H_k, own columns (zero for j <= k)
 #pragma unroll
   for (int cs = 0; cs < 8; ++cs) {
     const int j = a.c0 + 16 * cs;
-    double2 wv = cmk(0.0, 0.0), rv = cmk(0.0, 0.0);
-    if (cs >= CSK && j > k) {
-      rv = rowb[j];
-      if (!h.zero) {
-        const double2 yv = L.bd.w[j];
-        wv = cscale(cfms_conj_val(yv, h.beta, rv), h.inv);
-      }
+    // columns in slots above CSK are all right of column k; only slot CSK is masked
+    rj[cs] = (cs > CSK || (cs == CSK && j > k)) ? rowb[j] : cmk(0.0, 0.0);
+    wj[cs] = cmk(0.0, 0.0);
+  }
+  if (!h.zero) {  // uniform; one branch around the whole block
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) {
+      const int j = a.c0 + 16 * cs;
+      const double2 wv = cscale(cfms_conj_val(L.bd.w[j], h.beta, rj[cs]), h.inv);
+      wj[cs] = (cs > CSK || j > k) ? wv : cmk(0.0, 0.0);  // w_j = 0 for j <= k (y_k = |x|^2 is not w_k)
     }
-    wj[cs] = wv;
-    rj[cs] = rv;
   }
   {
     // u (zero when the column is already zero: H_k = I, stored as such)
@@ -792,9 +805,12 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
     for (int rs = 0; rs < 4; ++rs) {
       const int i = a.r0 + 32 * rs;
       double2 uv = cmk(0.0, 0.0);
-      if (rs >= RSK && i >= k && !h.zero) uv = i == k ? uk : cscale(x[rs], h.inv);
+      if (!h.zero) {
+        if (rs > RSK) uv = cscale(x[rs], h.inv);
+        else if (rs == RSK && i >= k) uv = i == k ? uk : cscale(x[rs], h.inv);
+      }
       u[rs] = uv;
-      if (a.trans && a.c0 == 0 && rs >= RSK && i >= k && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
+      if (a.trans && a.c0 == 0 && (rs > RSK || (rs == RSK && i >= k)) && i < a.p) a.Hg[(long)k * a.ldh + i] = uv;
     }
     if (!h.zero) {
 #pragma unroll
@@ -807,31 +823,43 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
   // ---- G_k on row k after H_k, columns k+1 .. q-1: every 16-lane row group
   // rebuilds the row from rowb and w (the owner's registers hold the same
   // values) and sums its norm, so no exchange is needed.
+  if (!h.zero) {
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) cfms(rj[cs], uk, wj[cs]);
+  }
   double s = 0.0;
 #pragma unroll
-  for (int cs = 0; cs < 8; ++cs) {
-    double2 r = rj[cs];
-    if (!h.zero) cfms(r, uk, wj[cs]);
-    rj[cs] = r;
-    s += cabs2(r);
-  }
-  s = row16_sum(s);
+  for (int cs = CSK; cs < 8; ++cs) s += cabs2(rj[cs]);
+  // the 16-lane sum's rounding depends on the lane; lane 0's value is used everywhere
+  s = uni(row16_sum(s));
   double2 rk1 = cmk(0.0, 0.0);
   if (k + 1 < a.q) {
     rk1 = rowb[k + 1];
     if (!h.zero) cfms(rk1, uk, cscale(cfms_conj_val(L.bd.w[k + 1], h.beta, rk1), h.inv));
+    rk1 = cmk(uni(rk1.x), uni(rk1.y));
   }
   const HhScalars g = hh_scalars(s, rk1);
   if (tid == 0) L.ec[k] = g.beta;
   // v (zero when the row is already zero: G_k = I, stored as such)
   double2 vv[8];
 #pragma unroll
-  for (int cs = 0; cs < 8; ++cs) {
-    const int j = a.c0 + 16 * cs;
-    double2 xv = cmk(0.0, 0.0);
-    if (cs >= CSK && j > k && !g.zero) xv = cconj(j == k + 1 ? cscale(g.ph, g.head) : cscale(rj[cs], g.inv));
-    vv[cs] = xv;
-    if (!a.trans && a.r0 == 0 && cs >= CSK && j > k && j < a.q) a.Hg[(long)k * a.ldh + j] = xv;
+  for (int cs = 0; cs < 8; ++cs) vv[cs] = cmk(0.0, 0.0);
+  if (!g.zero) {
+    // rj is zero for j <= k; column k + 1 (the pivot) lies in slot CSK or CSK + 1
+    const double2 head = cscale(g.ph, g.head);
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) {
+      const int j = a.c0 + 16 * cs;
+      const double2 xv = cscale(rj[cs], g.inv);
+      vv[cs] = cconj((cs <= CSK + 1 && j == k + 1) ? head : xv);
+    }
+  }
+  if (!a.trans && a.r0 == 0) {
+#pragma unroll
+    for (int cs = CSK; cs < 8; ++cs) {
+      const int j = a.c0 + 16 * cs;
+      if ((cs > CSK || j > k) && j < a.q) a.Hg[(long)k * a.ldh + j] = vv[cs];
+    }
   }
   if (g.zero) return;
   // z_i = sum_j X_ij v_j; rows are whole within a 16-lane row of the wave
@@ -844,7 +872,7 @@ __device__ __forceinline__ void bd_step(double2 (&X)[4][8], const int k, const B
       for (int cs = CSK; cs < 8; ++cs) cfma(acc, X[rs][cs], vv[cs]);
       acc.x = row16_sum(acc.x);
       acc.y = row16_sum(acc.y);
-      if (a.r0 + 32 * rs <= k) acc = cmk(0.0, 0.0);
+      if (rs == RSK && a.r0 + 32 * rs <= k) acc = cmk(0.0, 0.0);
     }
     zp[rs] = acc;
   }
@@ -877,15 +905,6 @@ struct SvdShape {
   bool trans;
   double cutoff;
 };
-
-// Values that are the same in every lane, moved to scalar registers so that
-// conditions on them compile to uniform branches (function arguments arrive in
-// vector registers and would otherwise count as divergent).
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ double uni(double x) {
-  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
-                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
-}
 
 __device__ __forceinline__ SvdShape svd_shape(int m, int nn, int D, double cutoff, int ws) {
   SvdShape sh;
