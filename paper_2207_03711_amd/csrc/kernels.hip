@@ -1262,45 +1262,39 @@ __device__ __noinline__ bool svd_vectors(GateLds& L, const SvdShape& sh, int kee
   double* Gb2 = Gb + 128 * kZS;
   for (int it = 0; it < 6; ++it) {
     {
-      // 4 x 4 tiles of the full Gram matrix; waves 0-3 and 4-7 split the rows of Y
-      const int tile = tid & 255, half = tid >> 8;
-      const int ta = tile >> 4, tc = tile & 15;
-      const bool act = 4 * ta < keep && 4 * tc < keep;
-      double acc[4][4] = {};
-      if (act) {
-        const int kh = (q + 1) >> 1;
-        const int k0 = half ? kh : 0, k1 = half ? q : kh;
-        for (int k = k0; k < k1; ++k) {
+      // G = Y^T Y (keep x keep) on FP64 MFMA 16x16x4 into Gb2: 16 x 16 tiles,
+      // up to two per wave, K = q in steps of 4
+      using Op = MfmaOps<double2>;
+      const int li = lane & 15, lk = lane >> 4;
+      const int nt = (keep + 15) >> 4;
+      for (int t = wave; t < nt * nt; t += 8) {
+        const int ti = t / nt, tj = t - ti * nt;
+        const int m = 16 * ti + li, n = 16 * tj + li;
+        mfma_d4 acc = mfma_d4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < q; k0 += 4) {
+          const int k = k0 + lk;
           const double* yr = Yb + (long)(2 * k) * kZS;
-          double ya[4], yc[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            ya[u] = yr[4 * ta + u];
-            yc[u] = yr[4 * tc + u];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], yc[w], acc[u][w]);
+          const double av = (k < q && m < keep) ? yr[m] : 0.0;  // A(m, k) = Y(k, m)
+          const double bv = (k < q && n < keep) ? yr[n] : 0.0;  // B(k, n) = Y(k, n)
+          acc = Op::mma(av, bv, acc);
         }
-        double* G = half ? Gb2 : Gb;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int w = 0; w < 4; ++w) G[(long)(2 * (4 * ta + u)) * kZS + 4 * tc + w] = acc[u][w];
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + Op::row(lk, r), col = 16 * tj + li;
+          if (row < keep && col < keep) Gb2[(long)(2 * row) * kZS + col] = acc[r];
+        }
       }
     }
     __syncthreads();
     {
-      // G = G1 + G2; err = max |G - I|; Gb <- 3/2 I - G/2 is kept for the refinement
+      // err = max |G - I|; Gb <- 3/2 I - G/2 is kept for the refinement
       double err = 0.0;
       for (int e = tid; e < keep * keep; e += blockDim.x) {
         const int ra = e / keep, rc = e - ra * keep;
         const long o = (long)(2 * ra) * kZS + rc;
-        const double g = Gb[o] + Gb2[o];
+        const double g = Gb2[o];
         const double d = g - (ra == rc ? 1.0 : 0.0);
         err = fmax(err, fabs(d));
-        Gb2[o] = g;
         Gb[o] = (ra == rc ? 1.0 : 0.0) - 0.5 * d;
       }
       if (!(err <= 1e300)) err = 1e300;  // NaN or Inf
@@ -1314,32 +1308,39 @@ __device__ __noinline__ bool svd_vectors(GateLds& L, const SvdShape& sh, int kee
     if (err >= 1e300) return false;
     if (err <= 1e-14) break;  // orthonormal to working precision
     if (err <= 1e-3) {
-      // Y <- Y C, C = Gb; 4 x 4 output tiles, computed before any is written
-      const int tr = tid >> 4, tc = tid & 15;
-      const bool act = 4 * tr < q && 4 * tc < keep;
-      double acc[4][4] = {};
-      if (act) {
-        for (int e = 0; e < keep; ++e) {
-          double ya[4], cc[4];
+      // Y <- Y C, C = Gb, on FP64 MFMA: 16 x 16 tiles of the q x keep product,
+      // up to four per wave, all computed before any is written
+      using Op = MfmaOps<double2>;
+      const int li = lane & 15, lk = lane >> 4;
+      const int ntr = (q + 15) >> 4, ntc = (keep + 15) >> 4;
+      mfma_d4 acc[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) ya[u] = Yb[(long)(2 * (4 * tr + u)) * kZS + e];
-#pragma unroll
-          for (int w = 0; w < 4; ++w) cc[w] = Gb[(long)(2 * e) * kZS + 4 * tc + w];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) acc[u][w] = fma(ya[u], cc[w], acc[u][w]);
+      for (int c = 0; c < 4; ++c) {
+        acc[c] = mfma_d4{0, 0, 0, 0};
+        const int t = wave + 8 * c;
+        if (t < ntr * ntc) {
+          const int ti = t / ntc, tj = t - ti * ntc;
+          const int i = 16 * ti + li, n = 16 * tj + li;
+          for (int e0 = 0; e0 < keep; e0 += 4) {
+            const int e = e0 + lk;
+            const double av = (i < q && e < keep) ? Yb[(long)(2 * i) * kZS + e] : 0.0;     // A(i, e) = Y(i, e)
+            const double bv = (e < keep && n < keep) ? Gb[(long)(2 * e) * kZS + n] : 0.0;  // B(e, n) = C(e, n)
+            acc[c] = Op::mma(av, bv, acc[c]);
+          }
         }
       }
       __syncthreads();
-      if (act) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int c = 0; c < 4; ++c) {
+        const int t = wave + 8 * c;
+        if (t < ntr * ntc) {
+          const int ti = t / ntc, tj = t - ti * ntc;
 #pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const int ra = 4 * tr + u, rc = 4 * tc + w;
-            if (ra < q && rc < keep) Yb[(long)(2 * ra) * kZS + rc] = acc[u][w];
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + Op::row(lk, r), col = 16 * tj + li;
+            if (row < q && col < keep) Yb[(long)(2 * row) * kZS + col] = acc[c][r];
           }
+        }
       }
       __syncthreads();
       // ||I - G||_2 <= keep * err; one step leaves about 0.75 (keep err)^2
