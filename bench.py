@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by what the same counters
 # read for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only
 # for the kernel source it was measured on (sha256 prefix); otherwise null.
-GATE_TRAFFIC = {"kernels_sha256": "0771523abe52b24e", "workload": "q16_d64", "precision": "fp64",
-                "bytes_per_launch": (2.0 * 1995.8 + 1.0 * 7339.6) * 1024.0}
+GATE_TRAFFIC = {"kernels_sha256": "54d2534dd620b066", "workload": "q16_d64", "precision": "fp64",
+                "bytes_per_launch": (2.0 * 1995.5 + 1.0 * 8034.3) * 1024.0}
 
 
 def measured_traffic(workload: str):
