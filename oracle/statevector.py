@@ -175,6 +175,30 @@ def grad_paramshift(n: int, n_elec: int, c_id, terms, rots, theta, pa=None,
     return grad, dphi
 
 
+def grad_fourterm(n: int, n_elec: int, c_id, terms, rots, theta, pa=None):
+    """Four-term shift per UCCSD parameter.  The rotations of one excitation
+    commute, so together they are exp(i theta_k G_k) with G_k = sum_m c_m P_m;
+    when G_k has eigenvalues in {0, +-1} (one-excitation rotations between two
+    determinants), E(theta_k) holds only the frequencies 1 and 2 and
+    dE/dtheta_k = D(pi/4) + (1 - sqrt 2) / 2 D(pi/2) exactly, with
+    D(s) = E(theta_k + s) - E(theta_k - s) (the general parameter-shift rule
+    for two frequencies)."""
+    pa = pa or PauliApplier(n)
+    theta = np.asarray(theta, dtype=float)
+    grad = np.zeros(len(theta))
+
+    def e_at(k, s):
+        th = theta.copy()
+        th[k] += s
+        return vqe_energy(n, n_elec, c_id, terms, rots, th, pa)
+
+    for k in range(len(theta)):
+        d1 = e_at(k, 0.5 * np.pi) - e_at(k, -0.5 * np.pi)
+        d2 = e_at(k, 0.25 * np.pi) - e_at(k, -0.25 * np.pi)
+        grad[k] = d2 + 0.5 * (1.0 - np.sqrt(2.0)) * d1
+    return grad
+
+
 def apply_two_site(psi: np.ndarray, n: int, site: int, g: np.ndarray) -> np.ndarray:
     """Apply a 4x4 gate (basis 2*i_site + i_{site+1}) to a dense state."""
     t = psi.reshape((1 << site, 4, 1 << (n - site - 2)))

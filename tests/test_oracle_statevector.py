@@ -86,6 +86,39 @@ def test_gradient_rules_agree():
         assert abs(fd - g_ad[k]) < 1e-7
 
 
+@pytest.mark.parametrize("n_orb,n_elec", [(2, 2), (3, 2), (3, 4), (4, 4)])
+def test_excitation_generators_have_spectrum_0_pm1(n_orb, n_elec):
+    """G_k = sum_m c_m P_m of every UCCSD parameter (its rotations combined)
+    has eigenvalues in {0, +-1}: built densely from Kronecker products of the
+    Pauli matrices, not through the oracle's Pauli code."""
+    n = 2 * n_orb
+    P = {(0, 0): np.eye(2), (1, 0): np.array([[0, 1], [1, 0]]), (1, 1): np.array([[0, -1j], [1j, 0]]),
+         (0, 1): np.diag([1.0, -1.0])}
+    rots = uccsd.rotations(n, n_elec)
+    for k in range(len(uccsd.excitations(n, n_elec))):
+        G = np.zeros((1 << n, 1 << n), dtype=complex)
+        for r in rots:
+            if r.param != k:
+                continue
+            M = np.ones((1, 1))
+            for q in reversed(range(n)):  # qubit 0 is the least significant bit of the index
+                M = np.kron(M, P[((r.x >> q) & 1, (r.z >> q) & 1)])
+            G += r.c * M
+        ev = np.linalg.eigvalsh(G)
+        assert np.all(np.min(np.abs(ev[:, None] - np.array([-1.0, 0.0, 1.0])[None, :]), axis=1) < 1e-12), k
+
+
+def test_fourterm_rule_equals_adjoint():
+    """The per-parameter four-term shift rule equals the exact gradient."""
+    for n_orb, n_elec, seed in ((2, 2, 71), (3, 4, 72)):
+        I, c_id, terms, rots = _problem(n_orb, n_elec, seed)
+        n = 2 * n_orb
+        th = random_theta(len(uccsd.excitations(n, n_elec)), seed + 1, amp=0.4)
+        g_ad, _, _ = sv.grad_adjoint(n, n_elec, c_id, terms, rots, th)
+        g_4 = sv.grad_fourterm(n, n_elec, c_id, terms, rots, th)
+        assert np.max(np.abs(g_ad - g_4)) < 1e-11
+
+
 @pytest.mark.parametrize("n_orb,seed", [(2, 61), (3, 62), (4, 63)])
 def test_norm_and_variational_bound(n_orb, seed):
     I, c_id, terms, rots = _problem(n_orb, n_orb, seed)
