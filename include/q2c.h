@@ -88,6 +88,11 @@ typedef struct {
                                1 -> fixed defaults                                         */
   const char* autotune_cache; /* nullable: text file of tuned choices, read at context
                                creation and appended to; the string is copied            */
+  int grad_rule;            /* vqe_grad_paramshift: 0 -> two-term shift of every rotation
+                               angle (2 circuits per rotation); 1 -> four-term shift of
+                               every UCCSD parameter (4 circuits per parameter; exact
+                               because the rotations of one excitation commute and their
+                               generator has eigenvalues 0, +-1)                          */
 } q2c_opts;
 
 /* Statistics of the last state evolution (all over the gates applied). */
@@ -241,13 +246,18 @@ int vqe_energy(vqe_problem* p, const double* theta, int n_theta, int max_bond, i
 int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_theta,
                      int max_bond, int precision, double* energies, q2c_stats* stats);
 
-/* Gradient by the two-term parameter shift of every rotation angle:
- * dE/dtheta_k = sum_{m in k} (-2 c_m) (E(phi_m + pi/2) - E(phi_m - pi/2)) / 2.
- * All shifted circuits (2 per rotation) and the unshifted one run as
- * batches of concurrent circuits; by default (q2c_opts.shift_from_start = 0)
- * the shifted circuits of a rotation start from the unshifted circuit's
- * state at that rotation's first angle-dependent gate, which leaves every
- * energy unchanged.  stats->gate_flops then counts every gate that ran once.
+/* Gradient by parameter shifts.  q2c_opts.grad_rule = 0: the two-term shift
+ * of every rotation angle,
+ * dE/dtheta_k = sum_{m in k} (-2 c_m) (E(phi_m + pi/2) - E(phi_m - pi/2)) / 2;
+ * grad_rule = 1: the four-term shift of every parameter,
+ * dE/dtheta_k = D(pi/4) + (1 - sqrt 2) / 2 D(pi/2), D(s) = E(theta_k + s) -
+ * E(theta_k - s).  Both are exact for the compiled circuit at full bond
+ * dimension.
+ * All shifted circuits and the unshifted one run as batches of concurrent
+ * circuits; by default (q2c_opts.shift_from_start = 0) each shifted circuit
+ * starts from the unshifted circuit's state at its first gate that depends
+ * on a shifted angle, which leaves every energy unchanged.
+ * stats->gate_flops then counts every gate that ran once.
  *   grad    n_theta doubles.
  *   energy  nullable; E(theta). */
 int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int max_bond,

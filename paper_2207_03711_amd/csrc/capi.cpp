@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <tuple>
 #include <memory>
@@ -89,7 +90,8 @@ struct vqe_problem {
   DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi, cursor, pairs;
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
          phi_cap = 0, cursor_cap = 0, pairs_cap = 0;
-  std::vector<int> fork_gate;  // per rotation: its first gate whose matrix depends on the rotation's angle
+  std::vector<int> fork_gate;   // per rotation: its first gate whose matrix depends on the rotation's angle
+  std::vector<int> param_fork;  // per parameter: the first fork gate of its rotations
   std::map<std::tuple<int, int>, std::unique_ptr<SlotStore>> snaps;  // (D, precision): fork snapshots
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<BatchGraph>> graphs;  // (D, slots, precision, fork)
 };
@@ -525,6 +527,7 @@ int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx**
     require(o.shift_from_start == 0 || o.shift_from_start == 1, "shift_from_start must be 0 or 1");
     require(o.eager_batches == 0 || o.eager_batches == 1, "eager_batches must be 0 or 1");
     require(o.no_autotune == 0 || o.no_autotune == 1, "no_autotune must be 0 or 1");
+    require(o.grad_rule == 0 || o.grad_rule == 1, "grad_rule must be 0 or 1");
     c->tuner.load(o.autotune_cache);
     o.autotune_cache = nullptr;  // the caller's string is not kept
     c->opts = o;
@@ -794,6 +797,11 @@ int vqe_problem_create(q2c_ctx* ctx, int n_orb, int n_elec, const double* h1, co
       }
       for (int f : p->fork_gate)
         if (f < 0) throw std::logic_error("rotation without an angle-dependent gate");
+      p->param_fork.assign(std::max(1, H.n_params), std::numeric_limits<int>::max());
+      for (size_t m = 0; m < H.rotations.size(); ++m) {
+        int& pf = p->param_fork[H.rotations[m].param];
+        pf = std::min(pf, p->fork_gate[m]);
+      }
       d.str_share = p->sshr.as<int>();
       hip_check(hipStreamSynchronize(st), "sync");
     }
@@ -916,20 +924,28 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
 }
 
 namespace {
-// Shifted-circuit energies, each circuit run from the start: (rot, +pi/2) and
-// (rot, -pi/2) for each listed rotation, then the unshifted circuit if
-// requested, in batches of the context's slot count.
-void shift_energies_from_start(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+// A shifted circuit: target t >= 0 shifts rotation angle phi_t, t = -2 - k
+// shifts parameter theta_k (every rotation of it); see launch_angles.
+struct ShiftCircuit {
+  int target;
+  double shift;
+};
+
+int fork_of(const vqe_problem* p, int target) {
+  return target >= 0 ? p->fork_gate[target] : p->param_fork[-2 - target];
+}
+
+// Energies of the shifted circuits, each run from the first gate, then of the
+// unshifted circuit if requested, in batches of the context's slot count.
+void shift_energies_from_start(vqe_problem* p, const double* theta, const std::vector<ShiftCircuit>& cs, int max_bond,
                                int precision, std::vector<double>& en, bool want_base, std::vector<double>& all_st,
                                PhaseTimes& pt) {
   const int np = p->host.n_params;
   std::vector<int> srot;
   std::vector<double> sval;
-  for (int m : rots) {
-    srot.push_back(m);
-    sval.push_back(0.5 * M_PI);
-    srot.push_back(m);
-    sval.push_back(-0.5 * M_PI);
+  for (const auto& c : cs) {
+    srot.push_back(c.target);
+    sval.push_back(c.shift);
   }
   if (want_base) {
     srot.push_back(-1);
@@ -953,15 +969,16 @@ void shift_energies_from_start(vqe_problem* p, const double* theta, const std::v
   }
 }
 
-// The same energies with the shared prefixes run once.  The shifted circuits
-// of rotation m agree with the unshifted one up to the first gate that
-// depends on phi_m, its fork gate.  One base slot runs the unshifted circuit
-// and its state is copied at the fork gate of each listed rotation; the two
-// shifted circuits of m start from that copy at their fork gate.  Rotations
-// are taken in fork order, slots/2 at a time, so the circuits of one batch
-// have about the same number of gates left; every gate runs as in a run from
-// the start, so the energies are the same bit for bit.
-void shift_energies_forked(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond,
+// The same energies with the shared prefixes run once.  A shifted circuit
+// agrees with the unshifted one up to the first gate that depends on its
+// shifted angle (rotation) or angles (parameter), its fork gate.  One base
+// slot runs the unshifted circuit and its state is copied at each fork gate;
+// the shifted circuits start from that copy at their fork gate.  Circuits are
+// taken in fork order, a batch of up to `slots` circuits with at most slots/2
+// distinct fork gates at a time, so the circuits of one batch have about the
+// same number of gates left; every gate runs as in a run from the start, so
+// the energies are the same bit for bit.
+void shift_energies_forked(vqe_problem* p, const double* theta, const std::vector<ShiftCircuit>& cs, int max_bond,
                            int precision, std::vector<double>& en, bool want_base, std::vector<double>& all_st,
                            PhaseTimes& pt) {
   q2c_ctx* ctx = p->ctx;
@@ -969,19 +986,19 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
   hipStream_t st = ctx->stream;
   const auto& H = p->host;
   const int np = H.n_params, n_gates = p->dev.n_gates;
-  const int nr = int(rots.size());
-  en.assign(2 * nr + (want_base ? 1 : 0), 0.0);
-  std::vector<int> ord(nr);
-  for (int i = 0; i < nr; ++i) ord[i] = i;
+  const int nc = int(cs.size());
+  en.assign(nc + (want_base ? 1 : 0), 0.0);
+  std::vector<int> ord(nc);
+  for (int i = 0; i < nc; ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(),
-                   [&](int a, int b) { return p->fork_gate[rots[a]] < p->fork_gate[rots[b]]; });
-  const int W = std::max(1, chunk_slots(p) / 2);
+                   [&](int a, int b) { return fork_of(p, cs[a].target) < fork_of(p, cs[b].target); });
+  const int C = chunk_slots(p), W = std::max(1, C / 2);
 
   // base slot: the unshifted circuit
   Batch& base = batch_for(p, max_bond, 1, precision);
   SlotStore& snaps = snap_store(p, max_bond, precision, W);
-  ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, 2 * W) * np));
-  ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(2 * W) * std::max(1, p->dev.n_rot));
+  ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, C) * np));
+  ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(C) * std::max(1, p->dev.n_rot));
   DBuf base_phi(ctx, sizeof(double) * std::max(1, p->dev.n_rot));
   q2c::DevBatch bd = base.d;
   bd.phi = base_phi.as<double>();
@@ -991,28 +1008,37 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
   int cur = 0;
   Events ev;
   std::vector<double> st_batch, e_batch;
-  for (int w0 = 0; w0 < nr; w0 += W) {
-    const int nw = std::min(W, nr - w0), nb = 2 * nw;
-    // the base slot advances to each fork gate of the window and is copied there
-    hip_check(hipEventRecord(ev.e[0], st), "event");
-    for (int i = 0; i < nw; ++i) {
-      const int f = p->fork_gate[rots[ord[w0 + i]]];
-      pt.gate_launches += run_gates(p, bd, cur, f, st);
-      cur = std::max(cur, f);
-      hip_check(q2c::launch_copy_slots(bd, snaps.d, nullptr, 1, make_int2(0, i), false, st), "snapshot");
+  for (int i0 = 0; i0 < nc;) {
+    // the batch: circuits ord[i0 .. i1), at most C of them and W distinct fork gates
+    std::vector<int> forks, snap_slot;
+    int i1 = i0;
+    while (i1 < nc && i1 - i0 < C) {
+      const int f = fork_of(p, cs[ord[i1]].target);
+      if (forks.empty() || f != forks.back()) {
+        if (int(forks.size()) == W) break;
+        forks.push_back(f);
+      }
+      snap_slot.push_back(int(forks.size()) - 1);
+      ++i1;
     }
-    // the window's shifted circuits, each from its copy and fork gate
+    const int nb = i1 - i0;
+    // the base slot advances to each fork gate of the batch and is copied there
+    hip_check(hipEventRecord(ev.e[0], st), "event");
+    for (size_t s = 0; s < forks.size(); ++s) {
+      pt.gate_launches += run_gates(p, bd, cur, forks[s], st);
+      cur = std::max(cur, forks[s]);
+      hip_check(q2c::launch_copy_slots(bd, snaps.d, nullptr, 1, make_int2(0, int(s)), false, st), "snapshot");
+    }
     std::vector<double> th(size_t(nb) * np), sval(nb);
-    std::vector<int> srot(nb), cursor(nb), snap_slot(nb);
+    std::vector<int> srot(nb), cursor(nb);
     std::vector<int2> pairs(nb);
     for (int j = 0; j < nb; ++j) {
-      const int m = rots[ord[w0 + j / 2]];
+      const ShiftCircuit& c = cs[ord[i0 + j]];
       std::copy(theta, theta + np, th.begin() + size_t(j) * np);
-      srot[j] = m;
-      sval[j] = (j % 2 == 0 ? 0.5 : -0.5) * M_PI;
-      cursor[j] = p->fork_gate[m];
-      snap_slot[j] = j / 2;
-      pairs[j] = make_int2(j / 2, j);
+      srot[j] = c.target;
+      sval[j] = c.shift;
+      cursor[j] = fork_of(p, c.target);
+      pairs[j] = make_int2(snap_slot[j], j);
     }
     e_batch.resize(nb);
     if (use_graphs(p)) {
@@ -1020,35 +1046,36 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
       run_graph(p, max_bond, precision, nb, true, th.data(), srot.data(), sval.data(), cursor.data(),
                 snap_slot.data(), &snaps, e_batch.data(), st_batch, pt);
       pt.gate_ms += ev.ms(0, 1);
-      for (int j = 0; j < nb; ++j) en[2 * ord[w0 + j / 2] + (j % 2)] = e_batch[j];
-      all_st.insert(all_st.end(), st_batch.begin(), st_batch.end());
-      continue;
+    } else {
+      Batch& B = batch_for(p, max_bond, nb, precision);
+      q2c::DevBatch db = B.d;
+      ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * nb);
+      ensure(ctx, p->shift_val, p->sval_cap, sizeof(double) * nb);
+      ensure(ctx, p->cursor, p->cursor_cap, sizeof(int) * nb);
+      ensure(ctx, p->pairs, p->pairs_cap, sizeof(int2) * nb);
+      if (np)
+        hip_check(hipMemcpyAsync(p->theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st),
+                  "copy theta");
+      hip_check(hipMemcpyAsync(p->shift_rot.p, srot.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy shifts");
+      hip_check(hipMemcpyAsync(p->shift_val.p, sval.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st),
+                "copy shifts");
+      hip_check(hipMemcpyAsync(p->cursor.p, cursor.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy cursor");
+      hip_check(hipMemcpyAsync(p->pairs.p, pairs.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, st), "copy pairs");
+      db.phi = p->phi.as<double>();
+      hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, p->shift_rot.as<int>(),
+                                   p->shift_val.as<double>(), st),
+                "angles");
+      hip_check(q2c::launch_copy_slots(snaps.d, db, p->pairs.as<int2>(), nb, make_int2(0, 0), true, st), "restore");
+      db.cursor = p->cursor.as<int>();
+      db.n_gates = n_gates;
+      pt.gate_launches += run_gates(p, db, 0, n_gates - forks.front(), st);
+      hip_check(hipEventRecord(ev.e[1], st), "event");
+      finish_circuits(p, B, db, nb, e_batch.data(), st_batch, pt);
+      pt.gate_ms += ev.ms(0, 1);
     }
-    Batch& B = batch_for(p, max_bond, nb, precision);
-    q2c::DevBatch db = B.d;
-    ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * nb);
-    ensure(ctx, p->shift_val, p->sval_cap, sizeof(double) * nb);
-    ensure(ctx, p->cursor, p->cursor_cap, sizeof(int) * nb);
-    ensure(ctx, p->pairs, p->pairs_cap, sizeof(int2) * nb);
-    if (np) hip_check(hipMemcpyAsync(p->theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st), "copy theta");
-    hip_check(hipMemcpyAsync(p->shift_rot.p, srot.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy shifts");
-    hip_check(hipMemcpyAsync(p->shift_val.p, sval.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st), "copy shifts");
-    hip_check(hipMemcpyAsync(p->cursor.p, cursor.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st), "copy cursor");
-    hip_check(hipMemcpyAsync(p->pairs.p, pairs.data(), sizeof(int2) * nb, hipMemcpyHostToDevice, st), "copy pairs");
-    db.phi = p->phi.as<double>();
-    hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, p->shift_rot.as<int>(),
-                                 p->shift_val.as<double>(), st),
-              "angles");
-    hip_check(q2c::launch_copy_slots(snaps.d, db, p->pairs.as<int2>(), nb, make_int2(0, 0), true, st), "restore");
-    db.cursor = p->cursor.as<int>();
-    db.n_gates = n_gates;
-    const int left = n_gates - p->fork_gate[rots[ord[w0]]];
-    pt.gate_launches += run_gates(p, db, 0, left, st);
-    hip_check(hipEventRecord(ev.e[1], st), "event");
-    finish_circuits(p, B, db, nb, e_batch.data(), st_batch, pt);
-    pt.gate_ms += ev.ms(0, 1);
-    for (int j = 0; j < nb; ++j) en[2 * ord[w0 + j / 2] + (j % 2)] = e_batch[j];
+    for (int j = 0; j < nb; ++j) en[ord[i0 + j]] = e_batch[j];
     all_st.insert(all_st.end(), st_batch.begin(), st_batch.end());
+    i0 = i1;
   }
   // the base slot's own energy, or only its statistics (its gates count once)
   std::vector<double> st_base(q2c::kNStats);
@@ -1056,7 +1083,7 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
     hip_check(hipEventRecord(ev.e[0], st), "event");
     pt.gate_launches += run_gates(p, bd, cur, n_gates, st);
     hip_check(hipEventRecord(ev.e[1], st), "event");
-    finish_circuits(p, base, bd, 1, &en[2 * nr], st_base, pt);
+    finish_circuits(p, base, bd, 1, &en[nc], st_base, pt);
     pt.gate_ms += ev.ms(0, 1);
   } else {
     std::vector<int> flag(1);
@@ -1071,22 +1098,16 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
   all_st.insert(all_st.end(), st_base.begin(), st_base.end());
 }
 
-void shift_energies(vqe_problem* p, const double* theta, const std::vector<int>& rots, int max_bond, int precision,
-                    std::vector<double>& ep, std::vector<double>& em, double* base, std::vector<double>& all_st,
+// Energies of the shifted circuits cs (in order), then the unshifted one if
+// base is given.
+void shift_energies(vqe_problem* p, const double* theta, const std::vector<ShiftCircuit>& cs, int max_bond,
+                    int precision, std::vector<double>& en, double* base, std::vector<double>& all_st,
                     PhaseTimes& pt) {
-  std::vector<double> en;
   if (p->ctx->opts.shift_from_start)
-    shift_energies_from_start(p, theta, rots, max_bond, precision, en, base != nullptr, all_st, pt);
+    shift_energies_from_start(p, theta, cs, max_bond, precision, en, base != nullptr, all_st, pt);
   else
-    shift_energies_forked(p, theta, rots, max_bond, precision, en, base != nullptr, all_st, pt);
-  const size_t nr = rots.size();
-  ep.resize(nr);
-  em.resize(nr);
-  for (size_t i = 0; i < nr; ++i) {
-    ep[i] = en[2 * i];
-    em[i] = en[2 * i + 1];
-  }
-  if (base) *base = en[2 * nr];
+    shift_energies_forked(p, theta, cs, max_bond, precision, en, base != nullptr, all_st, pt);
+  if (base) *base = en[cs.size()];
 }
 }  // namespace
 
@@ -1098,14 +1119,32 @@ int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int ma
     check_theta(p, theta, n_theta, 1);
     const auto t0 = std::chrono::steady_clock::now();
     const auto& R = p->host.rotations;
-    std::vector<int> rots(R.size());
-    for (size_t m = 0; m < R.size(); ++m) rots[m] = int(m);
-    std::vector<double> ep, em, all_st;
+    std::vector<ShiftCircuit> cs;
+    std::vector<double> en, all_st;
     PhaseTimes pt;
     double base = 0.0;
-    shift_energies(p, theta, rots, max_bond, precision, ep, em, energy ? &base : nullptr, all_st, pt);
     std::vector<double> g(n_theta, 0.0);
-    for (size_t m = 0; m < R.size(); ++m) g[R[m].param] += -2.0 * R[m].c * 0.5 * (ep[m] - em[m]);
+    if (p->ctx->opts.grad_rule == 0) {
+      // two-term shift of every rotation angle: dE/dphi_m = (E(phi_m + pi/2) - E(phi_m - pi/2)) / 2
+      for (size_t m = 0; m < R.size(); ++m) {
+        cs.push_back({int(m), 0.5 * M_PI});
+        cs.push_back({int(m), -0.5 * M_PI});
+      }
+      shift_energies(p, theta, cs, max_bond, precision, en, energy ? &base : nullptr, all_st, pt);
+      for (size_t m = 0; m < R.size(); ++m) g[R[m].param] += -2.0 * R[m].c * 0.5 * (en[2 * m] - en[2 * m + 1]);
+    } else {
+      // four-term shift of every parameter (its rotations commute and their
+      // generator has eigenvalues 0, +-1, so E(theta_k) has the frequencies 1
+      // and 2): dE/dtheta_k = D(pi/4) + (1 - sqrt 2) / 2 D(pi/2),
+      // D(s) = E(theta_k + s) - E(theta_k - s)
+      for (int k = 0; k < n_theta; ++k)
+        for (double sh : {0.5 * M_PI, -0.5 * M_PI, 0.25 * M_PI, -0.25 * M_PI}) cs.push_back({-2 - k, sh});
+      shift_energies(p, theta, cs, max_bond, precision, en, energy ? &base : nullptr, all_st, pt);
+      for (int k = 0; k < n_theta; ++k) {
+        const double d1 = en[4 * k] - en[4 * k + 1], d2 = en[4 * k + 2] - en[4 * k + 3];
+        g[k] = d2 + 0.5 * (1.0 - std::sqrt(2.0)) * d1;
+      }
+    }
     std::copy(g.begin(), g.end(), grad);
     if (energy) *energy = base;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1120,14 +1159,21 @@ int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const i
     require(rot_idx && e_plus && e_minus, "NULL argument");
     require(n_rot >= 1, "n_rot must be >= 1");
     check_theta(p, theta, n_theta, 1);
-    std::vector<int> rots(rot_idx, rot_idx + n_rot);
-    for (int m : rots) require(m >= 0 && m < int(p->host.rotations.size()), "rotation index out of range");
+    std::vector<ShiftCircuit> cs;
+    for (int i = 0; i < n_rot; ++i) {
+      const int m = rot_idx[i];
+      require(m >= 0 && m < int(p->host.rotations.size()), "rotation index out of range");
+      cs.push_back({m, 0.5 * M_PI});
+      cs.push_back({m, -0.5 * M_PI});
+    }
     const auto t0 = std::chrono::steady_clock::now();
-    std::vector<double> ep, em, all_st;
+    std::vector<double> en, all_st;
     PhaseTimes pt;
-    shift_energies(p, theta, rots, max_bond, precision, ep, em, nullptr, all_st, pt);
-    std::copy(ep.begin(), ep.end(), e_plus);
-    std::copy(em.begin(), em.end(), e_minus);
+    shift_energies(p, theta, cs, max_bond, precision, en, nullptr, all_st, pt);
+    for (int i = 0; i < n_rot; ++i) {
+      e_plus[i] = en[2 * i];
+      e_minus[i] = en[2 * i + 1];
+    }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_stats(stats, all_st, int(all_st.size() / q2c::kNStats), secs, pt);
   });

@@ -99,6 +99,9 @@ hipError_t launch_init_product(const DevBatch& b, const uint8_t* d_occ, hipStrea
 // slot), or the single pair `one` when d_pairs is null.
 hipError_t launch_copy_slots(const DevBatch& src, const DevBatch& dst, const int2* d_pairs, int n_pairs, int2 one,
                              bool clear_work, hipStream_t st);
+// phi_m = -2 c_m theta[param(m)] per slot; optional per-slot shift: target
+// t >= 0 adds the shift to phi_t, t = -2 - k adds it to theta_k (all rotations
+// of parameter k), t = -1 none.
 hipError_t launch_angles(const DevBatch& b, const DevProblem& p, const double* d_theta, int n_theta,
                          const int* d_shift_rot, const double* d_shift_val, hipStream_t st);
 hipError_t launch_gates(const DevBatch& b, const int* d_site, const int* d_rot, const double2* d_pre,

@@ -390,9 +390,17 @@ __global__ void k_angles(double* phi, int n_rot, const double* rot_c, const int*
   const int r = blockIdx.y, slot = slot0 + r;
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_rot) return;
-  double v = -2.0 * rot_c[m] * theta[(long)r * n_theta + rot_param[m]];
-  if (shift_rot && shift_rot[r] == m) v += shift_val[r];
-  phi[(long)slot * n_rot + m] = v;
+  const int k = rot_param[m];
+  double th = theta[(long)r * n_theta + k];
+  double add = 0.0;
+  if (shift_rot) {
+    // shift target: rotation t >= 0 (phi_t += shift), or parameter -2 - t
+    // (theta_k += shift for every rotation of that parameter); -1: none
+    const int t = shift_rot[r];
+    if (t == m) add = shift_val[r];
+    if (t == -2 - k) th += shift_val[r];
+  }
+  phi[(long)slot * n_rot + m] = -2.0 * rot_c[m] * th + add;
 }
 
 // ----------------------------------------------------------- gate kernel --

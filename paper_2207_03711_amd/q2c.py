@@ -48,6 +48,7 @@ class q2c_opts(C.Structure):
         ("eager_batches", C.c_int),
         ("no_autotune", C.c_int),
         ("autotune_cache", C.c_char_p),
+        ("grad_rule", C.c_int),
     ]
 
 
