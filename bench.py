@@ -218,7 +218,9 @@ def main():
     ap.add_argument("--serve", type=int, default=64, help="measured requests of the serving run (0 to skip)")
     ap.add_argument("--grad", choices=("fp64", "mixed"), default=None,
                     help="also measure the full parameter-shift gradient of the workload at this precision "
-                         "(2 circuits per rotation + 1, batches of --batch circuits; minutes at 16 qubits)")
+                         "(batches of --batch circuits; minutes at 16 qubits)")
+    ap.add_argument("--grad-rule", choices=("two", "four"), default="four",
+                    help="two: 2 circuits per rotation angle; four: 4 circuits per UCCSD parameter")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -360,15 +362,15 @@ def main():
             "roofline": {"kernel": "k_gates", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
                          "time": "batch-graph HIP events (gates + environments + sweeps)"},
-            "gradient_seconds_est_from_start": (2 * prob.info["n_rotations"] + 1) / (args.batch / dt),
-            "gradient_seconds_est_forked": fork_frac * (2 * prob.info["n_rotations"]) / (args.batch / dt)
+            "two_term_gradient_seconds_est_from_start": (2 * prob.info["n_rotations"] + 1) / (args.batch / dt),
+            "two_term_gradient_seconds_est_forked": fork_frac * (2 * prob.info["n_rotations"]) / (args.batch / dt)
             + out["ms_per_step"] / 1e3,
         }
         bprob.close()
         bctx.close()
     if args.grad:
         prec = q2c.Q2C_FP64 if args.grad == "fp64" else q2c.Q2C_MIXED
-        gctx = q2c.Context(0, slots=max(2, args.batch))
+        gctx = q2c.Context(0, slots=max(2, args.batch), grad_rule=1 if args.grad_rule == "four" else 0)
         gprob = q2c.Problem(gctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
         log(f"gradient ({args.grad}) ...")
         torch.cuda.synchronize()
@@ -380,10 +382,10 @@ def main():
         ach = stg["gate_flops"] / (dev_ms * 1e-3) / 1e12
         log(f"gradient: {dt:.1f}s, {stg['n_circuits']} circuits")
         out["gradient"] = {
-            "precision": args.grad, "seconds": dt, "circuits": stg["n_circuits"],
+            "precision": args.grad, "rule": args.grad_rule, "seconds": dt, "circuits": stg["n_circuits"],
             "circuits_per_s": stg["n_circuits"] / dt, "graph_launches": stg["graph_launches"],
             "tune_seconds": stg["tune_ms"] / 1e3,
-            "from_start_seconds_est": out.get("batched", {}).get("gradient_seconds_est_from_start"),
+            "from_start_seconds_est": (stg["n_circuits"] / out["batched"]["value"]) if "batched" in out else None,
             "energy": e_g, "grad_norm": float(np.linalg.norm(g)),
             "roofline": {"kernel": "k_gates", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,

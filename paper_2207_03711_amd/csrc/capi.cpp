@@ -92,8 +92,9 @@ struct vqe_problem {
          phi_cap = 0, cursor_cap = 0, pairs_cap = 0;
   std::vector<int> fork_gate;   // per rotation: its first gate whose matrix depends on the rotation's angle
   std::vector<int> param_fork;  // per parameter: the first fork gate of its rotations
-  std::map<std::tuple<int, int>, std::unique_ptr<SlotStore>> snaps;  // (D, precision): fork snapshots
-  std::map<std::tuple<int, int, int, int>, std::unique_ptr<BatchGraph>> graphs;  // (D, slots, precision, fork)
+  std::map<std::tuple<int, int, int>, std::unique_ptr<SlotStore>> snaps;  // (D, precision, 0/1): fork snapshots
+  // (D, slots, precision, kind): kind 0 from the Hartree-Fock state, 1 / 2 from snapshot store 0 / 1
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<BatchGraph>> graphs;
 };
 
 namespace {
@@ -304,12 +305,14 @@ void run_circuits(vqe_problem* p, int D, int precision, const double* theta, int
   pt.gate_ms += ev.ms(0, 1);
 }
 
-SlotStore& snap_store(vqe_problem* p, int D, int precision, int slots) {
-  auto key = std::make_tuple(D, precision);
+// Snapshot store idx (0 or 1) of shape (D, precision); fork graphs of kind
+// idx + 1 read it.
+SlotStore& snap_store(vqe_problem* p, int D, int precision, int slots, int idx) {
+  auto key = std::make_tuple(D, precision, idx);
   auto& ss = p->snaps[key];
   if (!ss || ss->d.n_slots < slots) {
     for (auto it = p->graphs.begin(); it != p->graphs.end();)  // fork graphs read the old store
-      it = (std::get<0>(it->first) == D && std::get<2>(it->first) == precision && std::get<3>(it->first))
+      it = (std::get<0>(it->first) == D && std::get<2>(it->first) == precision && std::get<3>(it->first) == idx + 1)
                ? p->graphs.erase(it)
                : std::next(it);
     ss.reset();
@@ -385,21 +388,22 @@ void capture_graph(vqe_problem* p, const Batch& B, BatchGraph& G, const SlotStor
 }
 
 // Runs nb circuits through the batch graph of their shape (captured on first
-// use): theta nb x n_params; per slot a shifted rotation (or -1) and shift,
-// a first gate (0, or the fork gate) and, in fork mode, the snapshot slot to
-// start from.  Writes energies and per-slot statistics.  After the first
-// replay of an untuned shape the Pauli sweep is tuned on the live state and
-// the graph re-captured if the choice changed.
-void run_graph(vqe_problem* p, int D, int precision, int nb, bool fork, const double* theta, const int* srot,
+// use): theta nb x n_params; per slot a shift target (see launch_angles) and
+// shift, a first gate (0, or the fork gate) and, for fork kinds 1 / 2, the
+// slot of snapshot store 0 / 1 to start from.  Writes energies and per-slot
+// statistics.  After the first replay of an untuned shape the Pauli sweep is
+// tuned on the live state and the graph re-captured if the choice changed.
+void run_graph(vqe_problem* p, int D, int precision, int nb, int fork_kind, const double* theta, const int* srot,
                const double* sval, const int* first_gate, const int* snap_slot, const SlotStore* snaps,
                double* energies, std::vector<double>& stats_out, PhaseTimes& pt) {
+  const bool fork = fork_kind != 0;
   q2c_ctx* ctx = p->ctx;
   ctx->activate();
   hipStream_t st = ctx->stream;
   const auto& H = p->host;
   const int np = H.n_params, ns = p->dev.n_strings;
   Batch& B = batch_for(p, D, nb, precision);
-  auto key = std::make_tuple(D, nb, precision, fork ? 1 : 0);
+  auto key = std::make_tuple(D, nb, precision, fork_kind);
   auto& gp = p->graphs[key];
   if (!gp) {
     auto G = std::make_unique<BatchGraph>();
@@ -547,6 +551,10 @@ int q2c_ctx_destroy(q2c_ctx* ctx) {
     ctx->activate();
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->aux) {
+      (void)hipStreamSynchronize(ctx->aux);
+      (void)hipStreamDestroy(ctx->aux);
+    }
     delete ctx;
   });
 }
@@ -910,7 +918,7 @@ int vqe_energy_batch(vqe_problem* p, const double* theta, int n_batch, int n_the
     for (int b0 = 0; b0 < n_batch; b0 += chunk) {
       const int nb = std::min(chunk, n_batch - b0);
       if (use_graphs(p))
-        run_graph(p, max_bond, precision, nb, false, theta + size_t(b0) * n_theta, nullptr, nullptr, nullptr, nullptr,
+        run_graph(p, max_bond, precision, nb, 0, theta + size_t(b0) * n_theta, nullptr, nullptr, nullptr, nullptr,
                   nullptr, out.data() + b0, st, pt);
       else
         run_circuits(p, max_bond, precision, theta + size_t(b0) * n_theta, nb, nullptr, nullptr, out.data() + b0, st,
@@ -960,7 +968,7 @@ void shift_energies_from_start(vqe_problem* p, const double* theta, const std::v
     const int nb = std::min(chunk, total - b0);
     for (int i = 0; i < nb; ++i) std::copy(theta, theta + np, th.begin() + size_t(i) * np);
     if (use_graphs(p))
-      run_graph(p, max_bond, precision, nb, false, th.data(), srot.data() + b0, sval.data() + b0, nullptr, nullptr,
+      run_graph(p, max_bond, precision, nb, 0, th.data(), srot.data() + b0, sval.data() + b0, nullptr, nullptr,
                 nullptr, en.data() + b0, st, pt);
     else
       run_circuits(p, max_bond, precision, th.data(), nb, srot.data() + b0, sval.data() + b0, en.data() + b0, st,
@@ -974,16 +982,19 @@ void shift_energies_from_start(vqe_problem* p, const double* theta, const std::v
 // shifted angle (rotation) or angles (parameter), its fork gate.  One base
 // slot runs the unshifted circuit and its state is copied at each fork gate;
 // the shifted circuits start from that copy at their fork gate.  Circuits are
-// taken in fork order, a batch of up to `slots` circuits with at most slots/2
-// distinct fork gates at a time, so the circuits of one batch have about the
-// same number of gates left; every gate runs as in a run from the start, so
-// the energies are the same bit for bit.
+// taken in fork order, a batch of up to slots - 4 circuits with at most
+// slots/2 distinct fork gates at a time, so the circuits of one batch have
+// about the same number of gates left; every gate runs as in a run from the
+// start, so the energies are the same bit for bit.  The base slot runs on the
+// context's second stream one batch ahead, into the other of two snapshot
+// stores, so its gates overlap the previous batch (the batch leaves a few
+// compute units free for its workgroup); events order the two streams.
 void shift_energies_forked(vqe_problem* p, const double* theta, const std::vector<ShiftCircuit>& cs, int max_bond,
                            int precision, std::vector<double>& en, bool want_base, std::vector<double>& all_st,
                            PhaseTimes& pt) {
   q2c_ctx* ctx = p->ctx;
   ctx->activate();
-  hipStream_t st = ctx->stream;
+  hipStream_t st = ctx->stream, sb = ctx->aux_stream();
   const auto& H = p->host;
   const int np = H.n_params, n_gates = p->dev.n_gates;
   const int nc = int(cs.size());
@@ -992,61 +1003,81 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
   for (int i = 0; i < nc; ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(),
                    [&](int a, int b) { return fork_of(p, cs[a].target) < fork_of(p, cs[b].target); });
-  const int C = chunk_slots(p), W = std::max(1, C / 2);
-
-  // base slot: the unshifted circuit
+  const int C = chunk_slots(p);
+  const int W = std::max(1, C / 2), Cb = std::max(1, C > 8 ? C - 4 : C);
+  // batches: circuits ord[lo .. hi), their distinct fork gates and each circuit's snapshot slot
+  struct Window {
+    int lo, hi;
+    std::vector<int> forks, snap_slot;
+  };
+  std::vector<Window> win;
+  for (int i0 = 0; i0 < nc;) {
+    Window w{i0, i0, {}, {}};
+    while (w.hi < nc && w.hi - i0 < Cb) {
+      const int f = fork_of(p, cs[ord[w.hi]].target);
+      if (w.forks.empty() || f != w.forks.back()) {
+        if (int(w.forks.size()) == W) break;
+        w.forks.push_back(f);
+      }
+      w.snap_slot.push_back(int(w.forks.size()) - 1);
+      ++w.hi;
+    }
+    i0 = w.hi;
+    win.push_back(std::move(w));
+  }
+  // base slot: the unshifted circuit, on the second stream
   Batch& base = batch_for(p, max_bond, 1, precision);
-  SlotStore& snaps = snap_store(p, max_bond, precision, W);
+  SlotStore* store[2] = {&snap_store(p, max_bond, precision, W, 0), &snap_store(p, max_bond, precision, W, 1)};
   ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, C) * np));
   ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(C) * std::max(1, p->dev.n_rot));
   DBuf base_phi(ctx, sizeof(double) * std::max(1, p->dev.n_rot));
+  DBuf base_theta(ctx, sizeof(double) * std::max(1, np));
   q2c::DevBatch bd = base.d;
   bd.phi = base_phi.as<double>();
-  if (np) hip_check(hipMemcpyAsync(p->theta.p, theta, sizeof(double) * np, hipMemcpyHostToDevice, st), "copy theta");
-  hip_check(q2c::launch_init_product(bd, p->occ.as<uint8_t>(), st), "init");
-  hip_check(q2c::launch_angles(bd, p->dev, p->theta.as<double>(), np, nullptr, nullptr, st), "angles");
+  if (np) hip_check(hipMemcpyAsync(base_theta.p, theta, sizeof(double) * np, hipMemcpyHostToDevice, sb), "copy theta");
+  hip_check(q2c::launch_init_product(bd, p->occ.as<uint8_t>(), sb), "init");
+  hip_check(q2c::launch_angles(bd, p->dev, base_theta.as<double>(), np, nullptr, nullptr, sb), "angles");
+  Events evb;  // base segments: e[0] .. e[1] around each; e[2]: base ready; e[3]: a batch done
   int cur = 0;
-  Events ev;
+  double base_ms = 0.0;
+  auto base_segment = [&](const Window& w, int idx) {
+    hip_check(hipEventRecord(evb.e[0], sb), "event");
+    for (size_t s = 0; s < w.forks.size(); ++s) {
+      pt.gate_launches += run_gates(p, bd, cur, w.forks[s], sb);
+      cur = std::max(cur, w.forks[s]);
+      hip_check(q2c::launch_copy_slots(bd, store[idx]->d, nullptr, 1, make_int2(0, int(s)), false, sb), "snapshot");
+    }
+    hip_check(hipEventRecord(evb.e[1], sb), "event");
+    hip_check(hipEventRecord(evb.e[2], sb), "event");
+  };
   std::vector<double> st_batch, e_batch;
-  for (int i0 = 0; i0 < nc;) {
-    // the batch: circuits ord[i0 .. i1), at most C of them and W distinct fork gates
-    std::vector<int> forks, snap_slot;
-    int i1 = i0;
-    while (i1 < nc && i1 - i0 < C) {
-      const int f = fork_of(p, cs[ord[i1]].target);
-      if (forks.empty() || f != forks.back()) {
-        if (int(forks.size()) == W) break;
-        forks.push_back(f);
-      }
-      snap_slot.push_back(int(forks.size()) - 1);
-      ++i1;
-    }
-    const int nb = i1 - i0;
-    // the base slot advances to each fork gate of the batch and is copied there
-    hip_check(hipEventRecord(ev.e[0], st), "event");
-    for (size_t s = 0; s < forks.size(); ++s) {
-      pt.gate_launches += run_gates(p, bd, cur, forks[s], st);
-      cur = std::max(cur, forks[s]);
-      hip_check(q2c::launch_copy_slots(bd, snaps.d, nullptr, 1, make_int2(0, int(s)), false, st), "snapshot");
-    }
+  if (!win.empty()) base_segment(win[0], 0);
+  for (size_t wi = 0; wi < win.size(); ++wi) {
+    const Window& w = win[wi];
+    const int idx = int(wi & 1), nb = w.hi - w.lo;
+    // this batch waits for its snapshots
+    hip_check(hipStreamWaitEvent(st, evb.e[2], 0), "wait");
+    hip_check(hipEventSynchronize(evb.e[1]), "sync");
+    base_ms += evb.ms(0, 1);
+    // the base slot runs ahead into the other store (free: the batch that read it has finished)
+    if (wi + 1 < win.size()) base_segment(win[wi + 1], 1 - idx);
     std::vector<double> th(size_t(nb) * np), sval(nb);
     std::vector<int> srot(nb), cursor(nb);
     std::vector<int2> pairs(nb);
     for (int j = 0; j < nb; ++j) {
-      const ShiftCircuit& c = cs[ord[i0 + j]];
+      const ShiftCircuit& c = cs[ord[w.lo + j]];
       std::copy(theta, theta + np, th.begin() + size_t(j) * np);
       srot[j] = c.target;
       sval[j] = c.shift;
       cursor[j] = fork_of(p, c.target);
-      pairs[j] = make_int2(snap_slot[j], j);
+      pairs[j] = make_int2(w.snap_slot[j], j);
     }
     e_batch.resize(nb);
     if (use_graphs(p)) {
-      hip_check(hipEventRecord(ev.e[1], st), "event");
-      run_graph(p, max_bond, precision, nb, true, th.data(), srot.data(), sval.data(), cursor.data(),
-                snap_slot.data(), &snaps, e_batch.data(), st_batch, pt);
-      pt.gate_ms += ev.ms(0, 1);
+      run_graph(p, max_bond, precision, nb, 1 + idx, th.data(), srot.data(), sval.data(), cursor.data(),
+                w.snap_slot.data(), store[idx], e_batch.data(), st_batch, pt);
     } else {
+      Events ev;
       Batch& B = batch_for(p, max_bond, nb, precision);
       q2c::DevBatch db = B.d;
       ensure(ctx, p->shift_rot, p->srot_cap, sizeof(int) * nb);
@@ -1065,26 +1096,35 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
       hip_check(q2c::launch_angles(db, p->dev, p->theta.as<double>(), np, p->shift_rot.as<int>(),
                                    p->shift_val.as<double>(), st),
                 "angles");
-      hip_check(q2c::launch_copy_slots(snaps.d, db, p->pairs.as<int2>(), nb, make_int2(0, 0), true, st), "restore");
+      hip_check(q2c::launch_copy_slots(store[idx]->d, db, p->pairs.as<int2>(), nb, make_int2(0, 0), true, st),
+                "restore");
       db.cursor = p->cursor.as<int>();
       db.n_gates = n_gates;
-      pt.gate_launches += run_gates(p, db, 0, n_gates - forks.front(), st);
+      hip_check(hipEventRecord(ev.e[0], st), "event");
+      pt.gate_launches += run_gates(p, db, 0, n_gates - w.forks.front(), st);
       hip_check(hipEventRecord(ev.e[1], st), "event");
       finish_circuits(p, B, db, nb, e_batch.data(), st_batch, pt);
       pt.gate_ms += ev.ms(0, 1);
     }
-    for (int j = 0; j < nb; ++j) en[ord[i0 + j]] = e_batch[j];
+    // the segment for window wi + 2 refills store idx: it waits until this
+    // batch (and its restore from that store) is done; the base tail does not
+    if (wi + 2 < win.size()) {
+      hip_check(hipEventRecord(evb.e[3], st), "event");
+      hip_check(hipStreamWaitEvent(sb, evb.e[3], 0), "wait");
+    }
+    for (int j = 0; j < nb; ++j) en[ord[w.lo + j]] = e_batch[j];
     all_st.insert(all_st.end(), st_batch.begin(), st_batch.end());
-    i0 = i1;
   }
   // the base slot's own energy, or only its statistics (its gates count once)
   std::vector<double> st_base(q2c::kNStats);
+  hip_check(hipEventRecord(evb.e[0], sb), "event");
+  if (want_base) pt.gate_launches += run_gates(p, bd, cur, n_gates, sb);
+  hip_check(hipEventRecord(evb.e[1], sb), "event");
+  hip_check(hipEventSynchronize(evb.e[1]), "sync");
+  base_ms += evb.ms(0, 1);
+  pt.gate_ms += base_ms;
   if (want_base) {
-    hip_check(hipEventRecord(ev.e[0], st), "event");
-    pt.gate_launches += run_gates(p, bd, cur, n_gates, st);
-    hip_check(hipEventRecord(ev.e[1], st), "event");
     finish_circuits(p, base, bd, 1, &en[nc], st_base, pt);
-    pt.gate_ms += ev.ms(0, 1);
   } else {
     std::vector<int> flag(1);
     hip_check(hipMemcpyAsync(st_base.data(), bd.stats, sizeof(double) * q2c::kNStats, hipMemcpyDeviceToHost, st),

@@ -143,11 +143,16 @@ struct q2c_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t aux = nullptr;  // second stream of the library's own (default priority), created on first use
   q2c_opts opts{};
   size_t bytes_in_use = 0;
   q2c_rt::Tuner tuner;
 
   void activate() const { hip_check(hipSetDevice(device), "hipSetDevice"); }
+  hipStream_t aux_stream() {
+    if (!aux) hip_check(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking), "hipStreamCreate");
+    return aux;
+  }
 
   void* dalloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
