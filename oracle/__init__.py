@@ -17,6 +17,8 @@ of what the GPU library computes, written from the paper's definitions:
                  (LAPACK SVD, truncation to D) and exact environment-based
                  Pauli expectations.
   exact.py       Brute-force ground-state energy (variational bound).
+  minimize.py    Local minimum of the UCCSD energy (the VQE outer loop's
+                 result) by a library minimiser on the exact gradient.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
 leg may import this package.  The product library never calls it, and it
