@@ -270,6 +270,47 @@ int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const i
                        int n_rot, int max_bond, int precision, double* e_plus, double* e_minus,
                        q2c_stats* stats);
 
+/* ---------------------------------------------------------------- VQE loop
+ * The variational outer loop (Sec. II-A: the energy of the ansatz state is
+ * handed to a classical optimizer that updates theta; the paper names none):
+ * L-BFGS (Nocedal & Wright, Alg. 7.4/7.5) with Armijo backtracking.  Every
+ * gradient is vqe_grad_paramshift (rule from q2c_opts.grad_rule) and the
+ * trial step lengths of one backtracking round are one vqe_energy_batch, so
+ * all circuits run on the device; the host only forms the search direction
+ * from n_theta-long vectors.  Zero fields take the defaults in brackets. */
+typedef struct {
+  int max_iter;     /* accepted steps at most                                   [100]  */
+  int history;      /* curvature pairs kept                                     [8]    */
+  int n_trial;      /* step lengths 1, 1/2, 1/4, ... per backtracking batch (<= 64) [4] */
+  double gtol;      /* converged when max_k |dE/dtheta_k| <= gtol                [1e-6] */
+  double ftol;      /* stop when a step lowers E by <= ftol max(1, |E|)         [1e-13] */
+  double max_step;  /* largest component of a steepest-descent step (radians)   [0.1]  */
+} q2c_min_opts;
+
+typedef struct {
+  int iterations;   /* accepted steps                                                   */
+  int grad_evals;   /* gradient calls (iterations + 1)                                  */
+  int energy_evals; /* line-search circuits                                             */
+  int status;       /* 1: gtol met; 2: ftol met; 0: max_iter reached; 3: no step of
+                       length >= 2^-(6 n_trial) lowered E (the energy's resolution)      */
+  double grad_max;  /* max_k |dE/dtheta_k| at theta_out                                  */
+  double seconds;   /* wall time                                                        */
+} q2c_min_report;
+
+/* Minimise E(theta) from theta0 at bond dimension max_bond.
+ *   theta0        n_theta starting parameters (n_theta = the problem's n_params).
+ *   opts          nullable (all defaults).
+ *   theta_out     n_theta doubles: the last accepted point (may equal theta0).
+ *   energy        nullable; E(theta_out).
+ *   energy_trace  nullable; room for max_iter + 1 doubles: E(theta0), then E
+ *                 after each accepted step (report->iterations + 1 written).
+ *   report        nullable.
+ * Non-convergence (status 0 or 3) is not an error.  Errors of the inner
+ * evaluations are returned unchanged, with nothing written. */
+int vqe_minimize(vqe_problem* p, const double* theta0, int n_theta, int max_bond, int precision,
+                 const q2c_min_opts* opts, double* theta_out, double* energy, double* energy_trace,
+                 q2c_min_report* report);
+
 /* ---------------------------------------------------------------- serving
  * A request server for independent fragment solves (the per-fragment VQE of
  * the DMET embedding, Sec. III-B; fragments are independent, Sec. III-C).

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/q2c.h"
+#include "compile.hpp"
 #include "engine.hpp"
 
 using q2c::cplx;

@@ -87,6 +87,31 @@ class q2c_stats(C.Structure):
         return d
 
 
+class q2c_min_opts(C.Structure):
+    _fields_ = [
+        ("max_iter", C.c_int),
+        ("history", C.c_int),
+        ("n_trial", C.c_int),
+        ("gtol", C.c_double),
+        ("ftol", C.c_double),
+        ("max_step", C.c_double),
+    ]
+
+
+class q2c_min_report(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int),
+        ("grad_evals", C.c_int),
+        ("energy_evals", C.c_int),
+        ("status", C.c_int),
+        ("grad_max", C.c_double),
+        ("seconds", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class q2c_server_opts(C.Structure):
     _fields_ = [("slots_per_class", C.c_int), ("gates_per_step", C.c_int)]
 
@@ -154,6 +179,8 @@ SIGNATURES = {
     "vqe_grad_paramshift": (C.c_int, [_vp, _pd, C.c_int, C.c_int, C.c_int, _pd, _pd, C.POINTER(q2c_stats)]),
     "vqe_shift_energies": (C.c_int, [_vp, _pd, C.c_int, _pi, C.c_int, C.c_int, C.c_int, _pd, _pd,
                                      C.POINTER(q2c_stats)]),
+    "vqe_minimize": (C.c_int, [_vp, _pd, C.c_int, C.c_int, C.c_int, C.POINTER(q2c_min_opts), _pd, _pd, _pd,
+                               C.POINTER(q2c_min_report)]),
     "q2c_server_create": (C.c_int, [_vp, C.POINTER(q2c_server_opts), _pvp]),
     "q2c_server_destroy": (C.c_int, [_vp]),
     "q2c_server_submit": (C.c_int, [_vp, C.c_uint64, C.c_int, C.c_int, _pd, _pd, C.c_double, _pd, C.c_int, C.c_int,
@@ -362,6 +389,23 @@ def vqe_shift_energies(p, theta, rot_idx, max_bond: int, precision: int = Q2C_FP
     return ep, em, st.as_dict()
 
 
+def vqe_minimize(p, theta0, max_bond: int, precision: int = Q2C_FP64, **opts):
+    """L-BFGS minimisation of E(theta) on the device: (theta, energy,
+    energy_trace, report dict).  opts: fields of q2c_min_opts."""
+    t = _f64(theta0)
+    o = q2c_min_opts()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    n_tr = (o.max_iter if o.max_iter > 0 else 100) + 1
+    out = np.zeros(len(t))
+    trace = np.zeros(n_tr)
+    e = C.c_double()
+    rep = q2c_min_report()
+    _check(lib.vqe_minimize(p, _dp(t), len(t), max_bond, precision, C.byref(o), _dp(out), C.byref(e), _dp(trace),
+                            C.byref(rep)))
+    return out, e.value, trace[: rep.iterations + 1].copy(), rep.as_dict()
+
+
 # ------------------------------------------------------------- handle classes
 
 
@@ -414,6 +458,9 @@ class Problem:
 
     def shift_energies(self, theta, rot_idx, max_bond: int, precision: int = Q2C_FP64):
         return vqe_shift_energies(self.h, theta, rot_idx, max_bond, precision)
+
+    def minimize(self, theta0, max_bond: int, precision: int = Q2C_FP64, **opts):
+        return vqe_minimize(self.h, theta0, max_bond, precision, **opts)
 
 
 class MPS:

@@ -125,8 +125,18 @@ def test_argument_errors():
     try:
         th = np.zeros(q2c.vqe_problem_info(p)["n_params"])
         _expect_error(lambda: q2c.vqe_energy(p, th, 4), q2c.Q2C_ERR_ARG)
+        # the VQE loop checks its own arguments, then passes the inner error through
+        _expect_error(lambda: q2c.vqe_minimize(p, th[:-1], 4), q2c.Q2C_ERR_ARG)
+        assert "n_theta" in q2c.last_error()
+        _expect_error(lambda: q2c.vqe_minimize(p, th, 4, n_trial=65), q2c.Q2C_ERR_ARG)
+        _expect_error(lambda: q2c.vqe_minimize(p, th, 4, gtol=-1.0), q2c.Q2C_ERR_ARG)
+        bad_th = th.copy()
+        bad_th[0] = np.nan
+        _expect_error(lambda: q2c.vqe_minimize(p, bad_th, 4), q2c.Q2C_ERR_ARG)
+        _expect_error(lambda: q2c.vqe_minimize(p, th, 4), q2c.Q2C_ERR_ARG)
     finally:
         q2c.vqe_problem_destroy(p)
+    assert q2c.lib.vqe_minimize(None, None, 0, 4, 0, None, None, None, None, None) == q2c.Q2C_ERR_ARG
 
 
 def test_context_without_gpu_reports_device_error():
