@@ -37,10 +37,11 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one launch of the gate kernel at the default workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by what the same counters
-# read for a 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only
-# for the kernel source it was measured on (sha256 prefix); otherwise null.
-GATE_TRAFFIC = {"kernels_sha256": "54d2534dd620b066", "workload": "q16_d64", "precision": "fp64",
-                "bytes_per_launch": (2.0 * 1995.5 + 1.0 * 8034.3) * 1024.0}
+# read for a 1 GiB device copy on the same machine (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  Valid only for the kernel source it was measured on
+# (sha256 prefix); otherwise null.
+GATE_TRAFFIC = {"kernels_sha256": "dd9c24decb18d4da", "workload": "q16_d64", "precision": "fp64",
+                "bytes_per_launch": (2.0 * 1995.5 + 1.0 * 7522.9) * 1024.0}
 
 
 def measured_traffic(workload: str):
@@ -204,6 +205,30 @@ def forked_gate_fraction(prob, slots):
     return work / (n_gates * len(fork))
 
 
+def vqe_curve(q2c, bonds=(2, 4, 8, 16)):
+    """Minimised UCCSD energy of the 8-qubit workload (4 orbitals, 4
+    electrons, integral seed 1001) from theta = 0 at each bond dimension;
+    D = 16 is exact for 8 qubits."""
+    cfg = CONFIGS["q8_d16"]
+    I = cfg.integrals()
+    ctx = q2c.Context(0, slots=128, grad_rule=1)
+    prob = q2c.Problem(ctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+    rows = []
+    try:
+        for D in bonds:
+            th0 = np.zeros(prob.info["n_params"])
+            _, e, trace, rep = prob.minimize(th0, D, q2c.Q2C_FP64, gtol=1e-7)
+            circuits = rep["grad_evals"] * (4 * prob.info["n_params"] + 1) + rep["energy_evals"]
+            log(f"vqe D={D}: E={e:.12f} {rep['iterations']} steps status {rep['status']} {rep['seconds']:.1f}s")
+            rows.append({"max_bond": D, "energy": e, "start_energy": float(trace[0]), "iterations": rep["iterations"],
+                         "status": rep["status"], "grad_max": rep["grad_max"], "seconds": rep["seconds"],
+                         "circuits": circuits, "circuits_per_s": circuits / rep["seconds"]})
+    finally:
+        prob.close()
+        ctx.close()
+    return {"workload": "q8_d16 integrals, theta0 = 0, L-BFGS, four-term gradient, FP64", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +246,9 @@ def main():
                          "(batches of --batch circuits; minutes at 16 qubits)")
     ap.add_argument("--grad-rule", choices=("two", "four"), default="four",
                     help="two: 2 circuits per rotation angle; four: 4 circuits per UCCSD parameter")
+    ap.add_argument("--vqe", action="store_true",
+                    help="also run the VQE loop (vqe_minimize, FP64, four-term gradient) on the 8-qubit workload "
+                         "from theta = 0 at D = 2, 4, 8, 16: minimum energy against bond dimension")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -414,6 +442,8 @@ def main():
         }
         gprob.close()
         gctx.close()
+    if args.vqe:
+        out["vqe_vs_bond"] = vqe_curve(q2c)
     if args.serve > 0:
         log("serving stream ...")
         out["serving"] = serve_bench(q2c, args.serve)
