@@ -205,6 +205,48 @@ def forked_gate_fraction(prob, slots):
     return work / (n_gates * len(fork))
 
 
+def gate_micro(q2c, D: int, seed: int = 11):
+    """Random nearest-neighbour two-qubit gates on a random MPS (the paper's
+    gate-application test, Sec. IV-C): n = 2 log2(D) + 2 qubits grown by
+    brickwork layers of random unitaries until the bonds next to the middle
+    one hold D, then gates on the middle bond, each an update of a 2D x 2D
+    two-site matrix, timed one by one (each call returns after its gate)."""
+    import math
+
+    n = 2 * int(math.log2(D)) + 2
+    rng = np.random.default_rng(seed)
+
+    def unitary():
+        z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        q, r = np.linalg.qr(z)
+        return q * (np.diag(r) / np.abs(np.diag(r)))
+
+    ctx = q2c.Context(0)
+    mps = q2c.MPS(ctx, [int(b) for b in rng.integers(0, 2, n)], D)
+    try:
+        for layer in range(int(math.log2(D)) + 6):
+            for site in range(layer % 2, n - 1, 2):
+                mps.apply_gate(site, unitary())
+        mid = n // 2 - 1
+        chi = mps.export()[0]
+        assert chi[mid] == D and chi[mid + 2] == D, list(chi)
+        k = {64: 200, 128: 40, 256: 12}.get(D, 8)
+        f0 = mps.stats()["gate_flops"]
+        t0 = time.perf_counter()
+        for _ in range(k):
+            mps.apply_gate(mid, unitary())
+        dt = time.perf_counter() - t0
+        flops = mps.stats()["gate_flops"] - f0
+    finally:
+        mps.close()
+        ctx.close()
+    ms = 1e3 * dt / k
+    log(f"gate micro D={D}: {2 * D}x{2 * D} two-site matrices, {ms:.2f} ms per gate")
+    return {"max_bond": D, "n_qubits": n, "matrix": 2 * D, "gates": k, "ms_per_gate": ms,
+            "gate_tflops": flops / dt / 1e12, "algorithmic_flops_per_gate": flops / k,
+            "svd": "bidiagonalisation + bisection" if D <= 64 else "one-sided Jacobi"}
+
+
 def vqe_curve(q2c, bonds=(2, 4, 8, 16)):
     """Minimised UCCSD energy of the 8-qubit workload (4 orbitals, 4
     electrons, integral seed 1001) from theta = 0 at each bond dimension;
@@ -249,6 +291,9 @@ def main():
     ap.add_argument("--vqe", action="store_true",
                     help="also run the VQE loop (vqe_minimize, FP64, four-term gradient) on the 8-qubit workload "
                          "from theta = 0 at D = 2, 4, 8, 16: minimum energy against bond dimension")
+    ap.add_argument("--gate-micro", type=str, default="", metavar="D[,D...]",
+                    help="only run the gate microbenchmark: random two-qubit gates on a random MPS whose middle "
+                         "bonds are saturated at each bond dimension D (<= 256), FP64, and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -265,9 +310,16 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the energy path has no multi-GPU mode in this build "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the energy path has no multi-GPU mode (circuits, fragments and "
+              "Pauli strings would be split over GPUs with one scalar reduction per evaluation)", file=sys.stderr)
         sys.exit(2)
+
+    if args.gate_micro:
+        from paper_2207_03711_amd import q2c
+
+        rows = [gate_micro(q2c, int(d)) for d in args.gate_micro.split(",")]
+        print(json.dumps({"gate_micro": rows, "dtype": "f64", "data": "synthetic"}), flush=True)
+        return
 
     os.environ.setdefault("Q2C_PROGRESS", "1")
     import torch
