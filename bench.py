@@ -205,6 +205,19 @@ def forked_gate_fraction(prob, slots):
     return work / (n_gates * len(fork))
 
 
+def gate_phase_split(cycles: dict) -> dict:
+    """Shares of the gate kernel's device cycles (its per-phase clock
+    counters, whole evaluation) in the two-site contraction (Eq. 7-8), the
+    SVD (Eq. 9: reduction to bidiagonal, values, vectors, back-transformation)
+    and the truncation + update (Eq. 10), beside the split the paper reports
+    for its Sunway runs (SVD about 82%, contraction about 15%, Sec. IV-C)."""
+    tot = sum(cycles.values())
+    svd = sum(cycles[k] for k in ("reduce", "values", "vectors", "back"))
+    return {"contract": cycles["contract"] / tot, "svd": svd / tot, "update": cycles["update"] / tot,
+            "svd_parts": {k: cycles[k] / tot for k in ("reduce", "values", "vectors", "back")},
+            "paper_sunway": {"svd": 0.82, "contract": 0.15}}
+
+
 def gate_micro(q2c, D: int, seed: int = 11):
     """Random nearest-neighbour two-qubit gates on a random MPS (the paper's
     gate-application test, Sec. IV-C): n = 2 log2(D) + 2 qubits grown by
@@ -385,6 +398,7 @@ def main():
         },
         "energy": energies[-1],
         "phase_ms_per_eval": {k: agg[k] / K for k in ("gate_ms", "env_ms", "pauli_ms", "reduce_ms")},
+        "gate_phase_split": gate_phase_split(st["cycles"]),
         "stats": {"max_chi": st["max_chi"], "discarded_weight_sum": st["discarded_weight_sum"],
                   "max_abs_imag": st["max_abs_imag"], "jacobi_sweeps_per_gate":
                   agg["jacobi_sweeps"] / K / prob.info["n_gates"], "max_sweeps_used": st["max_sweeps_used"]},

@@ -41,3 +41,10 @@ def test_forked_gate_fraction():
     assert abs(bench.forked_gate_fraction(p, 2) - np.mean(n - fork) / n) < 1e-12
     assert abs(bench.forked_gate_fraction(p, 10**6) - (n - fork.min()) / n) < 1e-12
     p.close()
+
+
+def test_gate_phase_split():
+    cyc = {"contract": 6.0, "reduce": 45.0, "values": 17.0, "vectors": 12.0, "back": 13.0, "update": 7.0}
+    s = bench.gate_phase_split(cyc)
+    assert abs(s["contract"] - 0.06) < 1e-15 and abs(s["svd"] - 0.87) < 1e-15 and abs(s["update"] - 0.07) < 1e-15
+    assert abs(sum(s["svd_parts"].values()) - s["svd"]) < 1e-15
