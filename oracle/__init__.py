@@ -19,6 +19,9 @@ of what the GPU library computes, written from the paper's definitions:
   exact.py       Brute-force ground-state energy (variational bound).
   minimize.py    Local minimum of the UCCSD energy (the VQE outer loop's
                  result) by a library minimiser on the exact gradient.
+  dmet.py        DMET chemical-potential loop (mean-field bath, embedded
+                 Hamiltonian, fragment electrons) around a UCCSD or exact
+                 fragment solver.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
 leg may import this package.  The product library never calls it, and it

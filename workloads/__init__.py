@@ -35,6 +35,8 @@ __all__ = [
     "serving_stream",
     "ServingRequest",
     "n_uccsd_params",
+    "Lattice",
+    "random_lattice",
 ]
 
 
@@ -195,3 +197,38 @@ def serving_stream(n: int, seed: int = 5000, k_range=(2, 8),
         mu = float(np.random.Generator(np.random.PCG64(700000 + r)).uniform(-0.5, 0.5))
         out.append(ServingRequest(r, k, d, mu, gap))
     return out
+
+
+@dataclasses.dataclass(frozen=True)
+class Lattice:
+    """A one-dimensional Hubbard-type lattice split into fragments: one-body
+    matrix h (hopping -t between neighbouring sites, on-site energies on the
+    diagonal), on-site repulsion U, n_elec electrons (even), fragments of
+    frag_size consecutive sites.  Stand-in for the lattice one-body models
+    around a DMET fragment (Sec. III-B); the paper's molecules are not
+    available."""
+
+    n_sites: int
+    frag_size: int
+    n_elec: int
+    h: np.ndarray  # (n_sites, n_sites) float64, symmetric
+    U: float
+
+    @property
+    def n_frags(self) -> int:
+        return self.n_sites // self.frag_size
+
+
+def random_lattice(n_sites: int, frag_size: int, n_elec: int, seed: int, t: float = 1.0,
+                   eps_amp: float = 0.5, U: float = 4.0, ring: bool = False) -> Lattice:
+    """On-site energies U[-eps_amp, eps_amp] (numpy PCG64(seed)), hopping -t on
+    the chain (and between the ends when ring)."""
+    if n_sites % frag_size or n_elec % 2 or not 0 < n_elec < 2 * n_sites:
+        raise ValueError("bad lattice shape")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = np.diag(rng.uniform(-eps_amp, eps_amp, n_sites)) if eps_amp > 0 else np.zeros((n_sites, n_sites))
+    for i in range(n_sites - 1):
+        h[i, i + 1] = h[i + 1, i] = -t
+    if ring and n_sites > 2:
+        h[0, n_sites - 1] = h[n_sites - 1, 0] = -t
+    return Lattice(n_sites, frag_size, n_elec, h, float(U))
