@@ -311,6 +311,68 @@ int vqe_minimize(vqe_problem* p, const double* theta0, int n_theta, int max_bond
                  const q2c_min_opts* opts, double* theta_out, double* energy, double* energy_trace,
                  q2c_min_report* report);
 
+/* ---------------------------------------------------------------- DMET loop
+ * The DMET procedure around the fragment solver (Sec. III-B): a low-level
+ * (restricted mean-field, U = 0) calculation of the whole lattice; for each
+ * fragment, bath orbitals from the Schmidt decomposition of that determinant
+ * and the Hamiltonian projected onto fragment + bath (2k orbitals, 2k
+ * electrons); the fragment problem minimised by vqe_minimize from theta = 0;
+ * the fragment's electron count from its one-particle density matrix at the
+ * minimum; the global chemical potential mu (entering as -mu times the
+ * fragment electron count) moved by regula falsi (Illinois) until the
+ * fragments' electrons add up to n_elec.  Fragment energy: the fragment's
+ * share of the one-body energy, 1/2 (P_F h + h P_F), plus its on-site
+ * interaction; the DMET energy is their sum.  Embedding orbitals: mean-field
+ * natural orbitals in fragment + bath, occupied first, each block
+ * diagonalising h, signs fixed by the largest site coefficient; U acts on
+ * the fragment sites only (non-interacting bath).  All circuits run on the
+ * device; the host does the n_sites-sized linear algebra. */
+typedef struct {
+  int n_sites;      /* L, 2 .. 64                                                */
+  int frag_size;    /* k, 1 .. 4, dividing L: fragments of k consecutive sites   */
+  int n_elec;       /* even, 2 .. 2L - 2                                         */
+  const double* h;  /* L x L row-major one-body matrix (symmetric, finite)       */
+  double U;         /* on-site repulsion U n_up n_down on every site             */
+} q2c_lattice;
+
+typedef struct {
+  double mu_lo, mu_hi; /* bracket with sum N_frag - n_elec <= 0 at mu_lo and >= 0
+                          at mu_hi; both 0 -> [-2, 2]                           */
+  double n_tol;        /* stop when |sum N_frag - n_elec| <= n_tol       [1e-6] */
+  int max_iter;        /* regula-falsi steps after the two bracket ends   [40]   */
+  int max_bond;        /* fragment MPS bond dimension [2^(2k): exact], <= 256    */
+  int precision;       /* Q2C_FP64 or Q2C_MIXED for the fragment circuits         */
+  q2c_min_opts vqe;    /* fragment VQE options (zero fields: defaults)           */
+} q2c_dmet_opts;
+
+typedef struct {
+  double mu;        /* chemical potential of the returned fragment results        */
+  double e_dmet;    /* sum of the fragment energies at mu                         */
+  int iterations;   /* regula-falsi steps                                          */
+  int status;       /* 1: converged; 0: max_iter reached; 3: the bracket ends
+                       have the same sign (results are those of mu_lo)            */
+  int vqe_runs;     /* fragment minimisations                                      */
+  double seconds;
+} q2c_dmet_report;
+
+/* Outputs (all nullable): n_frag, e_frag, e_emb with L/k doubles each (the
+ * fragments' electrons, fragment energies and embedded ground-state energies
+ * at the returned mu); mu_trace with room for max_iter + 2 doubles (every mu
+ * evaluated, bracket ends first).  Errors: Q2C_ERR_ARG for bad shapes or a
+ * degenerate mean field (no gap at the Fermi level, or a bath with fewer
+ * than k orbitals); inner errors are returned unchanged. */
+int dmet_solve(q2c_ctx* ctx, const q2c_lattice* lattice, const q2c_dmet_opts* opts, double* n_frag,
+               double* e_frag, double* e_emb, double* mu_trace, q2c_dmet_report* report);
+
+/* The embedded problem of fragment frag at chemical potential mu, as
+ * dmet_solve builds it (host only, no device): orbitals (L x 2k, row-major:
+ * site coefficients of the embedding orbitals), h1 ((2k)^2, including
+ * -mu times the fragment count), eri ((2k)^4, chemist (pq|rs)), nop ((2k)^2,
+ * one-body matrix of the fragment electron count), efrag_h1 ((2k)^2, one-body
+ * part of the fragment energy).  Every output is nullable. */
+int dmet_embedding(const q2c_lattice* lattice, int frag, double mu, double* orbitals, double* h1,
+                   double* eri, double* nop, double* efrag_h1);
+
 /* ---------------------------------------------------------------- serving
  * A request server for independent fragment solves (the per-fragment VQE of
  * the DMET embedding, Sec. III-B; fragments are independent, Sec. III-C).

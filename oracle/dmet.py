@@ -11,7 +11,8 @@ taken here:
 
 * Low level: the restricted determinant of the one-body lattice matrix h
   (U = 0), n_elec / 2 lowest orbitals doubly occupied; its per-spin density
-  matrix D = C_occ C_occ^T.
+  matrix D = C_occ C_occ^T.  A degenerate Fermi level (no unique
+  determinant) is an error.
 * Bath: the fragment's environment rows of D, D[E, F] = U s V^T; the k left
   singular vectors with s > 1e-10 span the bath (k = fragment size; fewer is
   an error).  Fragment + bath hold exactly k electrons per spin.
@@ -46,7 +47,10 @@ from . import statevector as sv
 
 def mean_field_density(lat) -> np.ndarray:
     w, C = np.linalg.eigh(lat.h)
-    occ = C[:, : lat.n_elec // 2]
+    no = lat.n_elec // 2
+    if no < lat.n_sites and abs(w[no] - w[no - 1]) < 1e-10:
+        raise ValueError("the mean-field determinant is degenerate (no gap at the Fermi level)")
+    occ = C[:, :no]
     return occ @ occ.T
 
 

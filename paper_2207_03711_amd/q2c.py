@@ -112,6 +112,42 @@ class q2c_min_report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class q2c_lattice(C.Structure):
+    _fields_ = [
+        ("n_sites", C.c_int),
+        ("frag_size", C.c_int),
+        ("n_elec", C.c_int),
+        ("h", C.POINTER(C.c_double)),
+        ("U", C.c_double),
+    ]
+
+
+class q2c_dmet_opts(C.Structure):
+    _fields_ = [
+        ("mu_lo", C.c_double),
+        ("mu_hi", C.c_double),
+        ("n_tol", C.c_double),
+        ("max_iter", C.c_int),
+        ("max_bond", C.c_int),
+        ("precision", C.c_int),
+        ("vqe", q2c_min_opts),
+    ]
+
+
+class q2c_dmet_report(C.Structure):
+    _fields_ = [
+        ("mu", C.c_double),
+        ("e_dmet", C.c_double),
+        ("iterations", C.c_int),
+        ("status", C.c_int),
+        ("vqe_runs", C.c_int),
+        ("seconds", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class q2c_server_opts(C.Structure):
     _fields_ = [("slots_per_class", C.c_int), ("gates_per_step", C.c_int)]
 
@@ -181,6 +217,9 @@ SIGNATURES = {
                                      C.POINTER(q2c_stats)]),
     "vqe_minimize": (C.c_int, [_vp, _pd, C.c_int, C.c_int, C.c_int, C.POINTER(q2c_min_opts), _pd, _pd, _pd,
                                C.POINTER(q2c_min_report)]),
+    "dmet_solve": (C.c_int, [_vp, C.POINTER(q2c_lattice), C.POINTER(q2c_dmet_opts), _pd, _pd, _pd, _pd,
+                             C.POINTER(q2c_dmet_report)]),
+    "dmet_embedding": (C.c_int, [C.POINTER(q2c_lattice), C.c_int, C.c_double, _pd, _pd, _pd, _pd, _pd]),
     "q2c_server_create": (C.c_int, [_vp, C.POINTER(q2c_server_opts), _pvp]),
     "q2c_server_destroy": (C.c_int, [_vp]),
     "q2c_server_submit": (C.c_int, [_vp, C.c_uint64, C.c_int, C.c_int, _pd, _pd, C.c_double, _pd, C.c_int, C.c_int,
@@ -404,6 +443,47 @@ def vqe_minimize(p, theta0, max_bond: int, precision: int = Q2C_FP64, **opts):
     _check(lib.vqe_minimize(p, _dp(t), len(t), max_bond, precision, C.byref(o), _dp(out), C.byref(e), _dp(trace),
                             C.byref(rep)))
     return out, e.value, trace[: rep.iterations + 1].copy(), rep.as_dict()
+
+
+def _lattice(n_sites: int, frag_size: int, n_elec: int, h, U: float):
+    hh = _f64(h).reshape(-1)
+    if hh.size != n_sites * n_sites:
+        raise ValueError("h must be n_sites x n_sites")
+    return q2c_lattice(n_sites, frag_size, n_elec, _dp(hh), float(U)), hh
+
+
+def dmet_embedding(n_sites: int, frag_size: int, n_elec: int, h, U: float, frag: int, mu: float = 0.0):
+    """Host-side embedded problem of one fragment: dict of orbitals (L x 2k),
+    h1, eri, nop, efrag_h1."""
+    lat, keep = _lattice(n_sites, frag_size, n_elec, h, U)
+    m = 2 * frag_size
+    out = {"orbitals": np.zeros((n_sites, m)), "h1": np.zeros((m, m)), "eri": np.zeros((m,) * 4),
+           "nop": np.zeros((m, m)), "efrag_h1": np.zeros((m, m))}
+    _check(lib.dmet_embedding(C.byref(lat), frag, float(mu), _dp(out["orbitals"]), _dp(out["h1"]), _dp(out["eri"]),
+                              _dp(out["nop"]), _dp(out["efrag_h1"])))
+    del keep
+    return out
+
+
+def dmet_solve(ctx, n_sites: int, frag_size: int, n_elec: int, h, U: float, mu_lo: float = 0.0, mu_hi: float = 0.0,
+               n_tol: float = 0.0, max_iter: int = 0, max_bond: int = 0, precision: int = Q2C_FP64, **vqe_opts):
+    """DMET chemical-potential loop on the device: dict with n_frag, e_frag,
+    e_emb (per fragment), mu_trace and the report fields."""
+    lat, keep = _lattice(n_sites, frag_size, n_elec, h, U)
+    o = q2c_dmet_opts()
+    o.mu_lo, o.mu_hi, o.n_tol, o.max_iter, o.max_bond, o.precision = mu_lo, mu_hi, n_tol, max_iter, max_bond, precision
+    for k, v in vqe_opts.items():
+        setattr(o.vqe, k, v)
+    nf = n_sites // frag_size
+    res = {"n_frag": np.zeros(nf), "e_frag": np.zeros(nf), "e_emb": np.zeros(nf)}
+    trace = np.full((max_iter if max_iter > 0 else 40) + 2, np.nan)
+    rep = q2c_dmet_report()
+    _check(lib.dmet_solve(ctx, C.byref(lat), C.byref(o), _dp(res["n_frag"]), _dp(res["e_frag"]), _dp(res["e_emb"]),
+                          _dp(trace), C.byref(rep)))
+    del keep
+    res["mu_trace"] = trace[~np.isnan(trace)]
+    res.update(rep.as_dict())
+    return res
 
 
 # ------------------------------------------------------------- handle classes

@@ -213,3 +213,38 @@ def test_pauli_prefix_order(which):
     assert shared == len(nodes)
     if which == "q16":
         assert shared < plain / 3.5
+
+
+@pytest.mark.parametrize("n_sites,k,seed", [(8, 1, 5), (8, 2, 3), (12, 3, 4), (12, 4, 6)])
+def test_dmet_embedding_matches_oracle(n_sites, k, seed):
+    """The C++ embedding (mean field, bath, natural orbitals, projected
+    integrals; its own Jacobi eigensolver) equals the oracle's (LAPACK) for
+    every fragment."""
+    from oracle import dmet
+    from workloads import random_lattice
+
+    lat = random_lattice(n_sites, k, n_sites, seed, U=3.0)
+    D = dmet.mean_field_density(lat)
+    for f in range(lat.n_frags):
+        N = dmet.embedding_basis(lat, D, f)
+        ref = dmet.embedded_problem(lat, N, f, 0.7)
+        got = q2c.dmet_embedding(n_sites, k, n_sites, lat.h, lat.U, f, 0.7)
+        assert np.max(np.abs(got["orbitals"] - N)) < 1e-10, f
+        for name in ("h1", "eri", "nop", "efrag_h1"):
+            assert np.max(np.abs(got[name] - getattr(ref, name))) < 1e-10, (f, name)
+
+
+def test_dmet_argument_errors():
+    from workloads import random_lattice
+
+    lat = random_lattice(8, 2, 8, 1)
+    _expect_error(lambda: q2c.dmet_embedding(8, 3, 8, lat.h, 1.0, 0), q2c.Q2C_ERR_ARG)  # k does not divide L
+    _expect_error(lambda: q2c.dmet_embedding(8, 2, 7, lat.h, 1.0, 0), q2c.Q2C_ERR_ARG)  # odd electrons
+    _expect_error(lambda: q2c.dmet_embedding(8, 2, 8, lat.h, 1.0, 4), q2c.Q2C_ERR_ARG)  # fragment index
+    bad = lat.h.copy()
+    bad[0, 1] += 1e-3
+    _expect_error(lambda: q2c.dmet_embedding(8, 2, 8, bad, 1.0, 0), q2c.Q2C_ERR_ARG)  # not symmetric
+    ring = random_lattice(8, 2, 8, 1, eps_amp=0.0, ring=True)
+    _expect_error(lambda: q2c.dmet_embedding(8, 2, 8, ring.h, 1.0, 0), q2c.Q2C_ERR_ARG)  # degenerate Fermi level
+    assert "degenerate" in q2c.last_error()
+    assert q2c.lib.dmet_solve(None, None, None, None, None, None, None, None) == q2c.Q2C_ERR_ARG

@@ -22,12 +22,12 @@ def test_no_interaction_is_exact(k, solver):
     assert np.max(np.abs(r.n_frag - want)) < 1e-6
 
 
-@pytest.mark.parametrize("ring", [False, True])
-def test_half_filling_particle_hole_symmetry(ring):
-    """Uniform bipartite chain or ring at half filling: particle-hole symmetry
-    maps the embedded problem at mu to the one at U - mu, so mu* = U/2 and
-    every fragment holds k electrons."""
-    lat = random_lattice(8, 2, 8, 1, eps_amp=0.0, U=4.0, ring=ring)
+@pytest.mark.parametrize("n_sites,ring", [(8, False), (6, True)])
+def test_half_filling_particle_hole_symmetry(n_sites, ring):
+    """Uniform bipartite chain or ring (6 sites: its Fermi level has a gap) at
+    half filling: particle-hole symmetry maps the embedded problem at mu to
+    the one at U - mu, so mu* = U/2 and every fragment holds k electrons."""
+    lat = random_lattice(n_sites, 2, n_sites, 1, eps_amp=0.0, U=4.0, ring=ring)
     r = dmet.dmet(lat, "fci", mu_lo=0.0, mu_hi=4.0)
     assert r.status == 1 and abs(r.mu - 2.0) < 1e-6
     assert np.max(np.abs(r.n_frag - 2.0)) < 1e-6
@@ -57,3 +57,10 @@ def test_two_electron_fragments_uccsd_equals_exact():
     assert ru.status == rf.status == 1
     assert abs(ru.mu - rf.mu) < 1e-6
     assert abs(ru.e_frag.sum() - rf.e_frag.sum()) < 1e-6
+
+
+def test_degenerate_fermi_level_is_an_error():
+    """The uniform 8-site ring at half filling has two orbitals at the Fermi
+    level: no unique mean-field determinant."""
+    with pytest.raises(ValueError):
+        dmet.mean_field_density(random_lattice(8, 2, 8, 1, eps_amp=0.0, ring=True))
