@@ -205,6 +205,44 @@ def forked_gate_fraction(prob, slots):
     return work / (n_gates * len(fork))
 
 
+def hadamard_baseline(q2c, sample: int = 8):
+    """The paper's measurement (a Hadamard-test circuit per Pauli string)
+    against one evolution plus transfer sweeps, on a 12-qubit problem (6
+    orbitals, 6 electrons, integral seed 1201, theta seed 1202) at D = 64,
+    exact for the 13-site state with the ancilla.  The paper's scheme reruns
+    the ansatz for every string: it is timed on `sample` strings and
+    extrapolated to all of them (stated in the output)."""
+    from workloads import n_uccsd_params, random_integrals, random_theta
+
+    I = random_integrals(6, 6, 1201)
+    th = random_theta(n_uccsd_params(6, 6), 1202)
+    ctx = q2c.Context(0)
+    prob = q2c.Problem(ctx, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+    try:
+        prob.energy(th, 64)  # first use: tuning and allocation
+        t0 = time.perf_counter()
+        e_sweep, st = prob.energy(th, 64)
+        t_sweep = time.perf_counter() - t0
+        e_had, _, t_shared = q2c.vqe_energy_hadamard(ctx.h, prob.h, th, 64, shared_state=True)
+        ns = prob.info["n_strings"]
+        pick = np.linspace(0, ns - 1, sample).astype(int)
+        _, _, t_pick = q2c.vqe_energy_hadamard(ctx.h, prob.h, th, 64, shared_state=False, string_idx=pick)
+    finally:
+        prob.close()
+        ctx.close()
+    per_string = t_pick / sample
+    log(f"hadamard 12 qubits: sweeps {t_sweep:.3f}s, shared-state Hadamard {t_shared:.1f}s, "
+        f"per-string circuits {per_string:.2f}s/string")
+    return {"workload": "12 qubits (6 orbitals, 6 electrons), integral seed 1201, theta seed 1202, D=64",
+            "n_strings": ns, "energy_sweeps": e_sweep, "energy_hadamard": e_had,
+            "energy_difference": e_had - e_sweep,
+            "seconds_sweeps": t_sweep, "pauli_sweep_ms": st["pauli_ms"], "seconds_hadamard_shared_state": t_shared,
+            "seconds_per_string_circuit": per_string,
+            "seconds_paper_scheme_extrapolated": per_string * ns,
+            "paper_scheme_sample": f"{sample} strings spread over the sorted list, extrapolated to {ns}",
+            "speedup_sweeps_vs_paper_scheme": per_string * ns / t_sweep}
+
+
 def gate_phase_split(cycles: dict) -> dict:
     """Shares of the gate kernel's device cycles (its per-phase clock
     counters, whole evaluation) in the two-site contraction (Eq. 7-8), the
@@ -304,6 +342,9 @@ def main():
     ap.add_argument("--vqe", action="store_true",
                     help="also run the VQE loop (vqe_minimize, FP64, four-term gradient) on the 8-qubit workload "
                          "from theta = 0 at D = 2, 4, 8, 16: minimum energy against bond dimension")
+    ap.add_argument("--hadamard", action="store_true",
+                    help="only run the Hadamard-test baseline (one circuit per Pauli string, the paper's "
+                         "measurement) against the transfer sweeps at 12 qubits, D = 64 (exact), and exit")
     ap.add_argument("--gate-micro", type=str, default="", metavar="D[,D...]",
                     help="only run the gate microbenchmark: random two-qubit gates on a random MPS whose middle "
                          "bonds are saturated at each bond dimension D (<= 256), FP64, and exit")
@@ -326,6 +367,13 @@ def main():
         print("bench.py measures one GPU: the energy path has no multi-GPU mode (circuits, fragments and "
               "Pauli strings would be split over GPUs with one scalar reduction per evaluation)", file=sys.stderr)
         sys.exit(2)
+
+    if args.hadamard:
+        from paper_2207_03711_amd import q2c
+
+        print(json.dumps({"hadamard_baseline": hadamard_baseline(q2c), "dtype": "f64", "data": "synthetic"}),
+              flush=True)
+        return
 
     if args.gate_micro:
         from paper_2207_03711_amd import q2c

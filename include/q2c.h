@@ -170,6 +170,11 @@ int mps_destroy(mps_state* s);
  *   discarded_weight  nullable; receives sum_{k>chi'} s_k^2 / sum_k s_k^2. */
 int mps_apply_gate(mps_state* s, int site, const double* gate, double* discarded_weight);
 
+/* Copy the state of src into dst on the device (site tensors, Schmidt
+ * values, bond dimensions, statistics).  Both must belong to one context and
+ * have the same qubits, max_bond and precision. */
+int mps_copy(mps_state* src, mps_state* dst);
+
 /* Expectation values <psi|P|psi> / <psi|psi> of Hermitian Pauli strings by
  * exact transfer-matrix contraction of the stored MPS (Eq. 2, Eq. 11).
  *   x_masks, z_masks  n_strings * n_words uint64 each, string-major.
@@ -221,6 +226,9 @@ int vqe_problem_destroy(vqe_problem* p);
 /* Sizes of a compiled problem (any pointer may be NULL). */
 int vqe_problem_info(const vqe_problem* p, int* n_qubits, int* n_params, int* n_strings,
                      int* n_rotations, int* n_gates, double* identity_coeff);
+/* Spatial orbitals and electrons the problem was created with (any pointer
+ * may be NULL); the Hartree-Fock state occupies qubits 0 .. n_elec-1. */
+int vqe_problem_electrons(const vqe_problem* p, int* n_orb, int* n_elec);
 /* Pauli strings in the order they are summed (ascending (x, z)), excluding
  * the identity; x, z: n_strings * n_words each; coeff: n_strings. */
 int vqe_problem_paulis(const vqe_problem* p, uint64_t* x, uint64_t* z, double* coeff);
@@ -269,6 +277,29 @@ int vqe_grad_paramshift(vqe_problem* p, const double* theta, int n_theta, int ma
 int vqe_shift_energies(vqe_problem* p, const double* theta, int n_theta, const int* rot_idx,
                        int n_rot, int max_bond, int precision, double* e_plus, double* e_minus,
                        q2c_stats* stats);
+
+/* The paper's own measurement, kept as the baseline the transfer sweeps
+ * replace (Sec. III-A after Eq. 11; the per-string circuits of Sec. III-D):
+ * for every Pauli string a Hadamard test on an ancillary qubit after the
+ * last qubit (site n_qubits of an (n_qubits + 1)-site MPS at max_bond, on
+ * ctx): Hartree-Fock state, ansatz gates, ancilla in |+>, the string applied
+ * under the ancilla's control as the ancilla moves down to the string's
+ * first qubit lo (n_qubits - lo gates, each a controlled letter and a swap),
+ * <X> of the ancilla = Re <psi|P|psi>.  Exact when max_bond holds the
+ * (n_qubits + 1)-site state (twice the ansatz state's bonds suffice).
+ *   p             any problem, also one created without a context (only its
+ *                 compiled strings, rotations and gates are read).
+ *   shared_state  0: every string's circuit runs the ansatz again (the
+ *                 paper's scheme); 1: the ansatz state is prepared once and
+ *                 copied on the device per string.  Same values bit for bit.
+ *   string_idx    nullable: the strings to measure (n_idx of them); NULL
+ *                 measures all and also writes energy (identity coefficient
+ *                 included, compensated sum in string order).
+ *   expect        nullable: one value per measured string.
+ *   seconds       nullable: wall time. */
+int vqe_energy_hadamard(q2c_ctx* ctx, vqe_problem* p, const double* theta, int n_theta, int max_bond,
+                        int precision, int shared_state, const int* string_idx, int n_idx, double* energy,
+                        double* expect, double* seconds);
 
 /* ---------------------------------------------------------------- VQE loop
  * The variational outer loop (Sec. II-A: the energy of the ansatz state is

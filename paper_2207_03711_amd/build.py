@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libq2c.so")
 
-SOURCES = ["kernels.hip", "capi.cpp", "compile.cpp", "server.cpp", "optimize.cpp", "dmet.cpp"]
+SOURCES = ["kernels.hip", "capi.cpp", "compile.cpp", "server.cpp", "optimize.cpp", "dmet.cpp", "hadamard.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = [

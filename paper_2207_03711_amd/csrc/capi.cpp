@@ -595,6 +595,21 @@ int mps_destroy(mps_state* s) {
   });
 }
 
+int mps_copy(mps_state* src, mps_state* dst) {
+  return guarded([&] {
+    require(src && dst, "NULL state");
+    require(src != dst, "src and dst are the same state");
+    require(src->ctx == dst->ctx, "src and dst belong to different contexts");
+    require(src->n == dst->n && src->D == dst->D && src->precision == dst->precision,
+            "src and dst differ in qubits, max_bond or precision");
+    q2c_ctx* ctx = src->ctx;
+    ctx->activate();
+    hip_check(q2c::launch_copy_slots(src->batch->d, dst->batch->d, nullptr, 1, make_int2(0, 0), false, ctx->stream),
+              "copy");
+    hip_check(hipStreamSynchronize(ctx->stream), "sync");
+  });
+}
+
 int mps_apply_gate(mps_state* s, int site, const double* gate, double* discarded_weight) {
   return guarded([&] {
     require(s && gate, "NULL argument");
@@ -838,6 +853,14 @@ int vqe_problem_info(const vqe_problem* p, int* n_qubits, int* n_params, int* n_
     if (n_rotations) *n_rotations = int(p->host.rotations.size());
     if (n_gates) *n_gates = int(p->host.gates.size());
     if (identity_coeff) *identity_coeff = p->host.c_identity;
+  });
+}
+
+int vqe_problem_electrons(const vqe_problem* p, int* n_orb, int* n_elec) {
+  return guarded([&] {
+    require(p != nullptr, "NULL problem");
+    if (n_orb) *n_orb = p->host.n_orb;
+    if (n_elec) *n_elec = p->host.n_elec;
   });
 }
 

@@ -217,6 +217,10 @@ SIGNATURES = {
                                      C.POINTER(q2c_stats)]),
     "vqe_minimize": (C.c_int, [_vp, _pd, C.c_int, C.c_int, C.c_int, C.POINTER(q2c_min_opts), _pd, _pd, _pd,
                                C.POINTER(q2c_min_report)]),
+    "mps_copy": (C.c_int, [_vp, _vp]),
+    "vqe_problem_electrons": (C.c_int, [_vp, _pi, _pi]),
+    "vqe_energy_hadamard": (C.c_int, [_vp, _vp, _pd, C.c_int, C.c_int, C.c_int, C.c_int, _pi, C.c_int, _pd, _pd,
+                                      _pd]),
     "dmet_solve": (C.c_int, [_vp, C.POINTER(q2c_lattice), C.POINTER(q2c_dmet_opts), _pd, _pd, _pd, _pd,
                              C.POINTER(q2c_dmet_report)]),
     "dmet_embedding": (C.c_int, [C.POINTER(q2c_lattice), C.c_int, C.c_double, _pd, _pd, _pd, _pd, _pd]),
@@ -443,6 +447,32 @@ def vqe_minimize(p, theta0, max_bond: int, precision: int = Q2C_FP64, **opts):
     _check(lib.vqe_minimize(p, _dp(t), len(t), max_bond, precision, C.byref(o), _dp(out), C.byref(e), _dp(trace),
                             C.byref(rep)))
     return out, e.value, trace[: rep.iterations + 1].copy(), rep.as_dict()
+
+
+def vqe_energy_hadamard(ctx, p, theta, max_bond: int, precision: int = Q2C_FP64, shared_state: bool = True,
+                        string_idx=None):
+    """Hadamard-test measurement, one circuit per string: (energy or None,
+    expectations, seconds)."""
+    t = _f64(theta)
+    n_strings = vqe_problem_info(p)["n_strings"]
+    idx = None if string_idx is None else np.ascontiguousarray(string_idx, dtype=np.int32)
+    ev = np.zeros(n_strings if idx is None else len(idx))
+    e = C.c_double(np.nan)
+    sec = C.c_double()
+    _check(lib.vqe_energy_hadamard(ctx, p, _dp(t), len(t), max_bond, precision, int(shared_state),
+                                   None if idx is None else idx.ctypes.data_as(_pi), 0 if idx is None else len(idx),
+                                   C.byref(e), _dp(ev), C.byref(sec)))
+    return (e.value if idx is None else None), ev, sec.value
+
+
+def mps_copy(src, dst) -> None:
+    _check(lib.mps_copy(src, dst))
+
+
+def vqe_problem_electrons(p):
+    no, ne = C.c_int(), C.c_int()
+    _check(lib.vqe_problem_electrons(p, C.byref(no), C.byref(ne)))
+    return no.value, ne.value
 
 
 def _lattice(n_sites: int, frag_size: int, n_elec: int, h, U: float):

@@ -134,6 +134,8 @@ def test_argument_errors():
         bad_th[0] = np.nan
         _expect_error(lambda: q2c.vqe_minimize(p, bad_th, 4), q2c.Q2C_ERR_ARG)
         _expect_error(lambda: q2c.vqe_minimize(p, th, 4), q2c.Q2C_ERR_ARG)
+        assert q2c.vqe_problem_electrons(p) == (2, 2)
+        _expect_error(lambda: q2c.vqe_energy_hadamard(None, p, th, 4), q2c.Q2C_ERR_ARG)
     finally:
         q2c.vqe_problem_destroy(p)
     assert q2c.lib.vqe_minimize(None, None, 0, 4, 0, None, None, None, None, None) == q2c.Q2C_ERR_ARG
