@@ -217,6 +217,9 @@ Embedded embed(const Lat& lat, const Mat& N, int f) {
 
 struct Problem {
   vqe_problem* p = nullptr;
+  Problem() = default;
+  Problem(const Problem&) = delete;
+  Problem& operator=(const Problem&) = delete;
   ~Problem() {
     if (p) vqe_problem_destroy(p);
   }

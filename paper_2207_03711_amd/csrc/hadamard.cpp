@@ -38,6 +38,9 @@ using C = std::complex<double>;
 
 struct Mps {
   mps_state* s = nullptr;
+  Mps() = default;
+  Mps(const Mps&) = delete;
+  Mps& operator=(const Mps&) = delete;
   ~Mps() {
     if (s) mps_destroy(s);
   }
