@@ -316,14 +316,21 @@ typedef struct {
   double gtol;      /* converged when max_k |dE/dtheta_k| <= gtol                [1e-6] */
   double ftol;      /* stop when a step lowers E by <= ftol max(1, |E|)         [1e-13] */
   double max_step;  /* largest component of a steepest-descent step (radians)   [0.1]  */
+  int no_speculation; /* 0: step length 1 is tried through the gradient call at the
+                       trial point (its unshifted circuit gives E there; accepted
+                       steps then cost one call, rejected ones continue with
+                       1/2, 1/4, ... in batches); 1: step length 1 is the first
+                       entry of the first batch.  The same steps either way.    */
 } q2c_min_opts;
 
 typedef struct {
   int iterations;   /* accepted steps                                                   */
-  int grad_evals;   /* gradient calls (iterations + 1)                                  */
+  int grad_evals;   /* gradient calls (iterations + 1, plus rejected trials of step
+                       length 1 when speculating)                                        */
   int energy_evals; /* line-search circuits                                             */
   int status;       /* 1: gtol met; 2: ftol met; 0: max_iter reached; 3: no step of
-                       length >= 2^-(6 n_trial) lowered E (the energy's resolution)      */
+                       length >= 2^-(6 n_trial) (2^-(6 n_trial + 1) when speculating)
+                       lowered E (the energy's resolution)                              */
   double grad_max;  /* max_k |dE/dtheta_k| at theta_out                                  */
   double seconds;   /* wall time                                                        */
 } q2c_min_report;

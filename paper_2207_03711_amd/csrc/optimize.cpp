@@ -9,7 +9,12 @@
 // whose largest component is max_step); backtracking on the Armijo condition
 // E(theta + a d) <= E + 1e-4 a g^T d with a = 1, 1/2, 1/4, ..., n_trial step
 // lengths evaluated at once as one batch of circuits and the largest
-// acceptable one taken; then the gradient at the new point.  A pair (s, y)
+// acceptable one taken; then the gradient at the new point.  By default step
+// length 1 is tried first through the gradient call at x + d, whose
+// unshifted circuit gives E(x + d) bit for bit as a batch would: an accepted
+// unit step then costs one call instead of a batch and a call, and a rejected
+// one continues the same sequence 1/2, 1/4, ... in batches, so the accepted
+// steps are the same.  A pair (s, y)
 // enters the memory only when s^T y > 1e-12 |s| |y| (Armijo alone does not
 // guarantee positive curvature); a non-descent direction clears the memory.
 #include <chrono>
@@ -114,7 +119,20 @@ int vqe_minimize(vqe_problem* p, const double* theta0, int n_theta, int max_bond
         slope = dot(g, d);
       }
       // backtracking, n_trial step lengths per batch
-      double a0 = 1.0, acc = 0.0, e_acc = 0.0;
+      double a0 = 1.0, acc = 0.0, e_acc = 0.0, En = 0.0;
+      bool have_grad = false;
+      if (!o.no_speculation) {
+        for (int k = 0; k < n_theta; ++k) xn[k] = x[k] + d[k];
+        call(vqe_grad_paramshift(p, xn.data(), n_theta, max_bond, precision, gn.data(), &En, nullptr));
+        rep.grad_evals += 1;
+        if (En <= E + kArmijo * slope) {
+          acc = 1.0;
+          e_acc = En;
+          have_grad = true;
+        } else {
+          a0 = 0.5;
+        }
+      }
       for (int round = 0; round < kRounds && acc == 0.0; ++round) {
         for (int j = 0; j < n_trial; ++j) {
           const double a = a0 * std::ldexp(1.0, -j);
@@ -136,11 +154,12 @@ int vqe_minimize(vqe_problem* p, const double* theta0, int n_theta, int max_bond
         status = 3;
         break;
       }
-      for (int k = 0; k < n_theta; ++k) xn[k] = x[k] + acc * d[k];
-      double En = 0.0;
-      call(vqe_grad_paramshift(p, xn.data(), n_theta, max_bond, precision, gn.data(), &En, nullptr));
-      (void)e_acc;  // the gradient call re-evaluates the same circuit; En is that energy
-      rep.grad_evals += 1;
+      if (!have_grad) {
+        for (int k = 0; k < n_theta; ++k) xn[k] = x[k] + acc * d[k];
+        call(vqe_grad_paramshift(p, xn.data(), n_theta, max_bond, precision, gn.data(), &En, nullptr));
+        rep.grad_evals += 1;
+      }
+      (void)e_acc;  // the gradient call evaluates the same circuit; En is that energy
       rep.iterations += 1;
       trace.push_back(En);
       std::vector<double> s(n_theta), y(n_theta);

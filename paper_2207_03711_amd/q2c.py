@@ -95,6 +95,7 @@ class q2c_min_opts(C.Structure):
         ("gtol", C.c_double),
         ("ftol", C.c_double),
         ("max_step", C.c_double),
+        ("no_speculation", C.c_int),
     ]
 
 
