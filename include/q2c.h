@@ -30,6 +30,9 @@
  *   On error no output is written and q2c_last_error() returns a message
  *   (thread-local, valid until the next call on that thread).  No C++
  *   exception crosses this boundary.
+ * Environment: Q2C_PROGRESS=1 prints a progress line to stderr after each
+ *   launch of gate runs longer than one launch (8,192 gates) and after each
+ *   batch graph that ran for at least a second.
  */
 #ifndef Q2C_H
 #define Q2C_H

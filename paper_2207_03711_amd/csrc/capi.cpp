@@ -133,7 +133,7 @@ int run_gates(vqe_problem* p, const q2c::DevBatch& db, int g0, int g1, hipStream
                                 db.cursor ? 0 : c0, db.cursor ? c1 - c0 : c1, p->dev.n_rot, sp, st),
               "gates");
     ++launches;
-    if (progress_enabled() && g1 - g0 >= 1024) {
+    if (progress_enabled() && g1 - g0 > kGateChunk) {  // runs of more than one launch
       hip_check(hipStreamSynchronize(st), "sync");
       std::fprintf(stderr, "[q2c] %d circuit(s): gates %d/%d done, %.1f s\n", db.n_slots, c1, g1,
                    std::chrono::duration<double>(std::chrono::steady_clock::now() - tp0).count());
@@ -454,7 +454,7 @@ void run_graph(vqe_problem* p, int D, int precision, int nb, int fork_kind, cons
   std::memcpy(energies, G.h_energy->p, sizeof(double) * nb);
   std::vector<int> flags(G.h_flags->as<int>(), G.h_flags->as<int>() + nb);
   stats_out.assign(G.h_stats->as<double>(), G.h_stats->as<double>() + size_t(nb) * q2c::kNStats);
-  if (progress_enabled()) {
+  if (progress_enabled() && ev.ms(0, 1) >= 1000.0) {  // long batches only
     std::fprintf(stderr, "[q2c] %d circuit(s): batch graph replayed, %.1f s\n", nb, ev.ms(0, 1) / 1e3);
     std::fflush(stderr);
   }
