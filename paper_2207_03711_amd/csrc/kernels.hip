@@ -1461,6 +1461,9 @@ __device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdSh
     vload(16 * (nblk - 1), nv);
 #pragma unroll
     for (int e = 0; e < 4; ++e) Vb[((nblk - 1) & 1) * 2048 + tid + 512 * e] = nv[e];
+    // a wave whose 16 columns are all at or beyond keep has W = 0 there, and
+    // it stays 0: it skips its products (no other wave reads its S rows)
+    const bool colact = 16 * ct < keep;
     for (int b = nblk - 1; b >= 0; --b) {
       const int k1 = 16 * b, st1 = trans ? k1 : k1 + 1;
       const double2* V = Vb + (b & 1) * 2048;
@@ -1468,11 +1471,13 @@ __device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdSh
       __syncthreads();  // V of this block (and every T) staged; the previous block's Sp reads are done
       if (b > 0) vload(k1 - 16, nv);  // next block's V, in flight during this one
       // -- partial S = V^H W over this wave's rows, for its 16 columns
-      {
+      if (colact) {
         Acc sr = Acc{0, 0, 0, 0}, si = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          if (64 * rh + 16 * t + 15 < st1) continue;  // the same for the whole wave
+          // the same for the whole wave: rows before the block's support, or
+          // at or beyond p (V and W are zero there)
+          if (64 * rh + 16 * t + 15 < st1 || 64 * rh + 16 * t >= p) continue;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = 64 * rh + 16 * t + 4 * r + lk;
@@ -1488,7 +1493,7 @@ __device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdSh
       }
       __syncthreads();
       // -- Z = T S for this wave's columns (both row halves compute it), then W -= V Z
-      {
+      if (colact) {
         Acc zr = Acc{0, 0, 0, 0}, zi = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
@@ -1502,7 +1507,7 @@ __device__ __noinline__ void svd_back(const SlotView& v, GateLds& L, const SvdSh
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          if (64 * rh + 16 * t + 15 < st1) continue;
+          if (64 * rh + 16 * t + 15 < st1 || 64 * rh + 16 * t >= p) continue;
           const int i = 64 * rh + 16 * t + li;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
