@@ -167,3 +167,38 @@ def test_fourterm_gradient(q2c):
         p_.close()
     for c in (c4, c4s, c2):
         c.close()
+
+
+@pytest.mark.parametrize("rule", [1, 0])
+def test_mixed_gradient_within_bar(q2c, rule):
+    """Mixed precision (complex64 contractions and sweeps, FP64 SVD and sums):
+    the parameter-shift gradient at full bond dimension (8 qubits, D = 16)
+    against the exact adjoint gradient, and forked batch graphs equal eager
+    from-start runs bit for bit.  The bar is the energy bar eps = 1e-5 Ha
+    carried through each rule's linear combination of energies: two-term
+    g_k = sum_m (-c_m)(E+_m - E-_m) with sum_m |c_m| = 1 for every UCCSD
+    parameter gives |dg| <= 2 eps; four-term D(pi/4) + (1 - sqrt 2)/2 D(pi/2)
+    gives |dg| <= 2 eps (1 + (sqrt 2 - 1)/2)."""
+    cfg = CONFIGS["q8_d16"]
+    I = cfg.integrals()
+    th = cfg.theta()
+    cg = q2c.Context(0, slots=64, grad_rule=rule)
+    ce = q2c.Context(0, slots=64, grad_rule=rule, shift_from_start=1, eager_batches=1)
+    pg, pe = _problem(q2c, cg, I), _problem(q2c, ce, I)
+    gm, em, _ = pg.grad(th, 16, q2c.Q2C_MIXED)
+    ge, ee, _ = pe.grad(th, 16, q2c.Q2C_MIXED)
+    assert np.array_equal(gm, ge) and em == ee
+    n = 8
+    c_id, terms = fermion.hamiltonian_terms(fermion.jw_hamiltonian(I.h1, I.eri))
+    rots = uccsd.rotations(n, 4)
+    g_ref, _, e_ref = sv.grad_adjoint(n, 4, c_id, terms, rots, th)
+    print(f"mixed gradient rule {rule}: max |g - g_exact| {np.max(np.abs(gm - g_ref)):.1e}, "
+          f"|E - E_exact| {abs(em - I.e_const - e_ref):.1e}", flush=True)
+    eps = 1e-5
+    bar = 2 * eps * (1 + (np.sqrt(2) - 1) / 2) if rule == 1 else 2 * eps
+    assert np.max(np.abs(gm - g_ref)) < bar
+    assert abs(em - I.e_const - e_ref) < eps
+    for p_ in (pg, pe):
+        p_.close()
+    for c in (cg, ce):
+        c.close()
