@@ -37,7 +37,8 @@ using Mat = std::vector<double>;  // row-major
 void sym_eig(int n, Mat a, std::vector<double>& w, Mat& V) {
   Mat U(size_t(n) * n, 0.0);
   for (int i = 0; i < n; ++i) U[size_t(i) * n + i] = 1.0;
-  for (int sweep = 0; sweep < 64; ++sweep) {
+  bool converged = false;
+  for (int sweep = 0; sweep <= 64; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {
@@ -45,7 +46,13 @@ void sym_eig(int n, Mat a, std::vector<double>& w, Mat& V) {
         tot += v;
         if (i != j) off += v;
       }
-    if (!(off > 1e-32 * tot)) break;
+    if (!std::isfinite(tot)) break;
+    // off-diagonal norm <= n 1e-15 of the whole: above what rounding leaves
+    if (!(off > (1e-30 * n * n) * tot)) {
+      converged = true;
+      break;
+    }
+    if (sweep == 64) break;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         const double apq = a[size_t(p) * n + q];
@@ -70,6 +77,7 @@ void sym_eig(int n, Mat a, std::vector<double>& w, Mat& V) {
         }
       }
   }
+  if (!converged) throw StatusError(Q2C_ERR_NUMERIC, "symmetric eigensolver did not converge in 64 Jacobi sweeps");
   std::vector<int> ord(n);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(),
