@@ -367,7 +367,9 @@ int vqe_minimize(vqe_problem* p, const double* theta0, int n_theta, int max_bond
  * natural orbitals in fragment + bath, occupied first, each block
  * diagonalising h, signs fixed by the largest site coefficient; U acts on
  * the fragment sites only (non-interacting bath).  All circuits run on the
- * device; the host does the n_sites-sized linear algebra. */
+ * device; the host does the n_sites-sized linear algebra.  Fragments are
+ * independent and are solved concurrently on worker contexts created on
+ * ctx's device with ctx's options. */
 typedef struct {
   int n_sites;      /* L, 2 .. 64                                                */
   int frag_size;    /* k, 1 .. 4, dividing L: fragments of k consecutive sites   */
@@ -384,6 +386,9 @@ typedef struct {
   int max_bond;        /* fragment MPS bond dimension [2^(2k): exact], <= 256    */
   int precision;       /* Q2C_FP64 or Q2C_MIXED for the fragment circuits         */
   q2c_min_opts vqe;    /* fragment VQE options (zero fields: defaults)           */
+  int workers;         /* fragments solved at once, each on a context (stream) of
+                          its own on ctx's device; results do not depend on it
+                          [min(8, fragments)]                                      */
 } q2c_dmet_opts;
 
 typedef struct {

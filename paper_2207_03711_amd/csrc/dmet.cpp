@@ -16,7 +16,9 @@
 // then the mean-field determinant.  Interaction U on the fragment sites only.
 #include <chrono>
 #include <cmath>
+#include <exception>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "runtime.hpp"
@@ -223,6 +225,18 @@ Embedded embed(const Lat& lat, const Mat& N, int f) {
   return e;
 }
 
+constexpr int kDmetWorkers = 8;  // concurrent fragment solves
+
+struct Ctx {
+  q2c_ctx* c = nullptr;
+  Ctx() = default;
+  Ctx(const Ctx&) = delete;
+  Ctx& operator=(const Ctx&) = delete;
+  ~Ctx() {
+    if (c) q2c_ctx_destroy(c);
+  }
+};
+
 struct Problem {
   vqe_problem* p = nullptr;
   Problem() = default;
@@ -293,13 +307,26 @@ int dmet_solve(q2c_ctx* ctx, const q2c_lattice* lat_in, const q2c_dmet_opts* opt
 
     const int nf = lat.L / lat.k;
     const Mat Dm = mean_field_density(lat);
+    // fragments are independent (the paper's first level of parallelism):
+    // W worker threads, each with a context (stream) of its own on the same
+    // device, solve fragments f = w, w + W, ... concurrently; each fragment's
+    // arithmetic is the same as alone, so the results do not depend on W
+    if (o.workers < 0) throw ArgError("workers must be >= 0");
+    const int W = std::min(nf, o.workers > 0 ? o.workers : kDmetWorkers);
+    std::vector<Ctx> workers(W);
+    {
+      q2c_opts wo = ctx->opts;
+      wo.autotune_cache = nullptr;
+      for (int w = 0; w < W; ++w) call(q2c_ctx_create(ctx->device, nullptr, &wo, &workers[w].c));
+    }
     std::vector<Embedded> emb;
     std::vector<Problem> pn(nf), pe(nf);
     const std::vector<double> zero(size_t(m) * m * m * m, 0.0);
     for (int f = 0; f < nf; ++f) {
       emb.push_back(embed(lat, embedding_basis(lat, Dm, f), f));
-      call(vqe_problem_create(ctx, m, m, emb[f].nop.data(), zero.data(), 0.0, &pn[f].p));
-      call(vqe_problem_create(ctx, m, m, emb[f].efrag.data(), emb[f].eri.data(), 0.0, &pe[f].p));
+      q2c_ctx* c = workers[f % W].c;
+      call(vqe_problem_create(c, m, m, emb[f].nop.data(), zero.data(), 0.0, &pn[f].p));
+      call(vqe_problem_create(c, m, m, emb[f].efrag.data(), emb[f].eri.data(), 0.0, &pe[f].p));
     }
     int np = 0;
     call(vqe_problem_info(pn[0].p, nullptr, &np, nullptr, nullptr, nullptr, nullptr));
@@ -311,20 +338,35 @@ int dmet_solve(q2c_ctx* ctx, const q2c_lattice* lat_in, const q2c_dmet_opts* opt
     };
     auto evaluate = [&](double mu) {
       Eval ev{0.0, std::vector<double>(nf), std::vector<double>(nf), std::vector<double>(nf)};
-      const std::vector<double> th0(np, 0.0);
-      std::vector<double> th(np);
+      std::vector<std::exception_ptr> err(W);
+      auto work = [&](int w) {
+        try {
+          q2c_ctx* c = workers[w].c;
+          const std::vector<double> th0(np, 0.0);
+          std::vector<double> th(np);
+          for (int f = w; f < nf; f += W) {
+            Mat h1 = emb[f].hbase;
+            for (size_t i = 0; i < h1.size(); ++i) h1[i] -= mu * emb[f].nop[i];
+            Problem ph;
+            call(vqe_problem_create(c, m, m, h1.data(), emb[f].eri.data(), 0.0, &ph.p));
+            call(vqe_minimize(ph.p, th0.data(), np, D, o.precision, &o.vqe, th.data(), &ev.eemb[f], nullptr,
+                              nullptr));
+            call(vqe_energy(pn[f].p, th.data(), np, D, o.precision, &ev.nfrag[f], nullptr));
+            call(vqe_energy(pe[f].p, th.data(), np, D, o.precision, &ev.efrag[f], nullptr));
+          }
+        } catch (...) {
+          err[w] = std::current_exception();
+        }
+      };
+      std::vector<std::thread> threads;
+      for (int w = 1; w < W; ++w) threads.emplace_back(work, w);
+      work(0);
+      for (auto& t : threads) t.join();
+      for (auto& e : err)
+        if (e) std::rethrow_exception(e);
       double total = 0.0;
-      for (int f = 0; f < nf; ++f) {
-        Mat h1 = emb[f].hbase;
-        for (size_t i = 0; i < h1.size(); ++i) h1[i] -= mu * emb[f].nop[i];
-        Problem ph;
-        call(vqe_problem_create(ctx, m, m, h1.data(), emb[f].eri.data(), 0.0, &ph.p));
-        call(vqe_minimize(ph.p, th0.data(), np, D, o.precision, &o.vqe, th.data(), &ev.eemb[f], nullptr, nullptr));
-        call(vqe_energy(pn[f].p, th.data(), np, D, o.precision, &ev.nfrag[f], nullptr));
-        call(vqe_energy(pe[f].p, th.data(), np, D, o.precision, &ev.efrag[f], nullptr));
-        total += ev.nfrag[f];
-        rep.vqe_runs += 1;
-      }
+      for (int f = 0; f < nf; ++f) total += ev.nfrag[f];
+      rep.vqe_runs += nf;
       ev.f = total - lat.ne;
       trace.push_back(mu);
       return ev;

@@ -132,6 +132,7 @@ class q2c_dmet_opts(C.Structure):
         ("max_bond", C.c_int),
         ("precision", C.c_int),
         ("vqe", q2c_min_opts),
+        ("workers", C.c_int),
     ]
 
 
@@ -497,12 +498,14 @@ def dmet_embedding(n_sites: int, frag_size: int, n_elec: int, h, U: float, frag:
 
 
 def dmet_solve(ctx, n_sites: int, frag_size: int, n_elec: int, h, U: float, mu_lo: float = 0.0, mu_hi: float = 0.0,
-               n_tol: float = 0.0, max_iter: int = 0, max_bond: int = 0, precision: int = Q2C_FP64, **vqe_opts):
+               n_tol: float = 0.0, max_iter: int = 0, max_bond: int = 0, precision: int = Q2C_FP64, workers: int = 0,
+               **vqe_opts):
     """DMET chemical-potential loop on the device: dict with n_frag, e_frag,
     e_emb (per fragment), mu_trace and the report fields."""
     lat, keep = _lattice(n_sites, frag_size, n_elec, h, U)
     o = q2c_dmet_opts()
     o.mu_lo, o.mu_hi, o.n_tol, o.max_iter, o.max_bond, o.precision = mu_lo, mu_hi, n_tol, max_iter, max_bond, precision
+    o.workers = workers
     for k, v in vqe_opts.items():
         setattr(o.vqe, k, v)
     nf = n_sites // frag_size

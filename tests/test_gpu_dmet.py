@@ -48,6 +48,17 @@ def test_dmet_matches_oracle(q2c, n_sites, k, seed):
     assert r["mu_trace"][0] == 0.0 and r["mu_trace"][1] == 4.0
 
 
+def test_dmet_workers_do_not_change_results(q2c):
+    """Fragments solved one at a time and eight at a time (each worker on a
+    context of its own) give the same results bit for bit."""
+    lat = random_lattice(8, 1, 8, 5, U=4.0)
+    r1 = _gpu(q2c, lat, mu_lo=0.0, mu_hi=4.0, workers=1)
+    r8 = _gpu(q2c, lat, mu_lo=0.0, mu_hi=4.0)
+    assert r1["mu"] == r8["mu"] and r1["iterations"] == r8["iterations"]
+    for k in ("n_frag", "e_frag", "e_emb", "mu_trace"):
+        assert np.array_equal(r1[k], r8[k]), k
+
+
 def test_dmet_without_interaction_is_exact(q2c):
     """U = 0: the loop stops at mu = 0 with the mean-field fragment electrons."""
     lat = random_lattice(8, 1, 8, 5, U=0.0)
