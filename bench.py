@@ -127,7 +127,7 @@ def arrival_times(stream, rate):
     return list(np.cumsum([r.arrival_gap for r in stream]) / rate)
 
 
-def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=0.7, warmup=16):
+def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=0.7, warmup=16, precision=None):
     """Poisson stream of fragment solves through the request server.
 
     Fragment size k ~ U{k_range} (embedded problem: 2k orbitals, 4k qubits),
@@ -137,6 +137,8 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
     Latency is submit-to-result on the host clock (problem compile, queueing
     and device time)."""
     from workloads import serving_stream
+
+    prec = q2c.Q2C_FP64 if precision is None else precision
 
     reqs = serving_stream(n_req + warmup, seed=seed, k_range=k_range, bonds=bonds)
     ctx = q2c.Context(0)
@@ -151,7 +153,7 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
                 r = pending[i][1]
                 I = r.integrals()
                 srv.submit(r.index, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), r.max_bond,
-                           q2c.Q2C_FP64, r.n_frag_orb)
+                           prec, r.n_frag_orb)
                 i += 1
             srv.step()
             for x in srv.poll():
@@ -174,13 +176,16 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
         classes.setdefault(key, []).append(x["done_s"] - x["submit_s"])
     ctx.close()
     return {
+        "precision": "fp64" if prec == q2c.Q2C_FP64 else "mixed",
+        "energies": {int(r.index): float(x["energy"]) for r, x in zip(reqs[warmup:], measured)},
         "requests": len(measured), "errors": len(bad), "evals_per_s": len(measured) / span,
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
         "capacity_evals_per_s": capacity, "offered_load": load, "arrival_rate_per_s": rate,
         "per_class": {k: {"n": len(v), "p50_s": float(np.percentile(v, 50)), "p99_s": float(np.percentile(v, 99))}
                       for k, v in sorted(classes.items())},
         "workload": (f"fragment solves: k ~ U{{{k_range[0]}..{k_range[1]}}} fragment orbitals embedded in 2k "
-                     f"orbitals ({4 * k_range[0]}-{4 * k_range[1]} qubits), D ~ U{list(bonds)}, FP64, "
+                     f"orbitals ({4 * k_range[0]}-{4 * k_range[1]} qubits), D ~ U{list(bonds)}, "
+                     f"{'FP64' if prec == q2c.Q2C_FP64 else 'mixed precision'}, "
                      f"Poisson arrivals at {load} of the measured capacity, {warmup} warm-up requests excluded"),
     }
 
@@ -563,6 +568,18 @@ def main():
         out["serving"] = serve_bench(q2c, args.serve)
         log(f"serving: {out['serving']['evals_per_s']:.2f} evals/s p50 {out['serving']['p50_s']:.2f}s "
             f"p99 {out['serving']['p99_s']:.2f}s")
+        if not args.no_mixed:
+            sm = serve_bench(q2c, args.serve, precision=q2c.Q2C_MIXED)
+            e64 = out["serving"].pop("energies")
+            emx = sm.pop("energies")
+            dev = np.array([abs(emx[k] - e64[k]) for k in e64])
+            sm["speedup_vs_fp64_serving"] = sm["evals_per_s"] / out["serving"]["evals_per_s"]
+            sm["abs_energy_minus_fp64"] = {"median": float(np.median(dev)), "max": float(dev.max()),
+                                           "n_within_1e-5": int((dev <= 1e-5).sum()), "n": int(dev.size)}
+            out["serving_mixed"] = sm
+            log(f"serving mixed: {sm['evals_per_s']:.2f} evals/s p50 {sm['p50_s']:.2f}s p99 {sm['p99_s']:.2f}s")
+        else:
+            out["serving"].pop("energies")
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(cfg, flops_eval, args.cpu_seconds)
