@@ -359,9 +359,18 @@ int dmet_solve(q2c_ctx* ctx, const q2c_lattice* lat_in, const q2c_dmet_opts* opt
         }
       };
       std::vector<std::thread> threads;
-      for (int w = 1; w < W; ++w) threads.emplace_back(work, w);
-      work(0);
-      for (auto& t : threads) t.join();
+      {
+        // joins every started worker on every path (also when starting one throws)
+        struct Joiner {
+          std::vector<std::thread>& t;
+          ~Joiner() {
+            for (auto& x : t)
+              if (x.joinable()) x.join();
+          }
+        } joiner{threads};
+        for (int w = 1; w < W; ++w) threads.emplace_back(work, w);
+        work(0);
+      }
       for (auto& e : err)
         if (e) std::rethrow_exception(e);
       double total = 0.0;
