@@ -133,18 +133,19 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
     Fragment size k ~ U{k_range} (embedded problem: 2k orbitals, 4k qubits),
     D ~ U{bonds}, DMET chemical-potential shift on the fragment orbitals.  The
     server's capacity is measured first on a closed batch of the same request
-    mix; arrivals then follow the stream's exponential gaps at load * capacity.
-    Latency is submit-to-result on the host clock (problem compile, queueing
-    and device time)."""
+    mix; arrivals then follow the stream's exponential gaps at load * capacity,
+    on the same server (its request classes and their slot memory already
+    exist, as in a running service).  Latency is submit-to-result on the host
+    clock (problem compile, queueing and device time)."""
     from workloads import serving_stream
 
     prec = q2c.Q2C_FP64 if precision is None else precision
 
     reqs = serving_stream(n_req + warmup, seed=seed, k_range=k_range, bonds=bonds)
     ctx = q2c.Context(0)
+    srv = q2c.Server(ctx, slots_per_class=64, gates_per_step=512)
 
     def run(stream, rate):
-        srv = q2c.Server(ctx, slots_per_class=64, gates_per_step=512)
         pending = list(zip(arrival_times(stream, rate), stream))
         res, t0, i = {}, time.perf_counter(), 0
         while len(res) < len(stream):
@@ -159,13 +160,13 @@ def serve_bench(q2c, n_req, seed=5000, k_range=(2, 3), bonds=(16, 32, 64), load=
             for x in srv.poll():
                 res[x["tag"]] = x
             time.sleep(0.0005)
-        srv.close()
         return res, time.perf_counter() - t0
 
     cap_res, cap_t = run(reqs[:warmup], 0.0)
     capacity = len(cap_res) / cap_t
     rate = load * capacity
     res, wall = run(reqs, rate)
+    srv.close()
     measured = [res[r.index] for r in reqs[warmup:]]
     bad = [x for x in measured if x["status"] != 0]
     lat = np.array([x["done_s"] - x["submit_s"] for x in measured])

@@ -149,6 +149,10 @@ typedef struct {
  * Returns Q2C_ERR_DEVICE if the device is absent or is not gfx950. */
 int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx** out);
 int q2c_ctx_destroy(q2c_ctx* ctx);
+/* Device memory the library holds for ctx (problems, MPS, batches, server
+ * classes, scratch) and the budget it may not exceed (q2c_opts
+ * hbm_budget_bytes); either pointer may be NULL. */
+int q2c_ctx_memory(const q2c_ctx* ctx, size_t* bytes_in_use, size_t* budget_bytes);
 
 /* Matrix product state in a product state (Eq. 6 with every bond of
  * dimension 1, e.g. the Hartree-Fock reference of Sec. III-D prepared by X
@@ -426,7 +430,9 @@ int dmet_embedding(const q2c_lattice* lattice, int frag, double mu, double* orbi
  * slot batch on the device sharing the UCCSD gate list; every slot carries
  * its own Hamiltonian, parameters and gate cursor.  q2c_server_step()
  * retires finished slots, admits queued requests into free slots (creating a
- * class when the context's HBM budget allows) and launches the next gate
+ * class when the context's HBM budget allows; idle classes stay allocated for
+ * later requests of their shape and are evicted, least recently used first,
+ * only when a new class does not fit) and launches the next gate
  * chunk of every class on that class's own stream, so classes overlap on the
  * device and requests join while others run (continuous batching).  Each
  * result depends only on its own request: served alone or in any mix it is

@@ -545,6 +545,14 @@ int q2c_ctx_create(int device, void* hip_stream, const q2c_opts* opts, q2c_ctx**
   });
 }
 
+int q2c_ctx_memory(const q2c_ctx* ctx, size_t* bytes_in_use, size_t* budget_bytes) {
+  return guarded([&] {
+    require(ctx != nullptr, "NULL context");
+    if (bytes_in_use) *bytes_in_use = ctx->bytes_in_use;
+    if (budget_bytes) *budget_bytes = ctx->opts.hbm_budget_bytes;
+  });
+}
+
 int q2c_ctx_destroy(q2c_ctx* ctx) {
   return guarded([&] {
     require(ctx != nullptr, "NULL context");

@@ -38,6 +38,7 @@ struct SrvClass {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool in_flight = false;
+  uint64_t last_use = 0;  // server step of the last admission or launch (eviction order)
 
   ~SrvClass() {
     if (stream) {
@@ -69,11 +70,19 @@ struct q2c_server {
   std::map<ClassKey, std::unique_ptr<SrvClass>> classes;
   std::deque<std::unique_ptr<SrvRequest>> queue;
   std::deque<q2c_result> ready;
+  uint64_t steps = 0;  // completed q2c_server_step calls
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
 namespace {
+
+// Whether a queued request waits for the class `key`.
+bool class_queued(const q2c_server* srv, const ClassKey& key) {
+  for (const auto& r : srv->queue)
+    if (ClassKey{r->prob.n_qubits, r->prob.n_elec, r->D, r->precision} == key) return true;
+  return false;
+}
 
 template <class T>
 void upload(q2c_ctx* ctx, DBuf& buf, const std::vector<T>& v, hipStream_t st) {
@@ -322,12 +331,29 @@ int q2c_server_step(q2c_server* srv, int* n_queued, int* n_active, int* n_ready)
       const ClassKey key{r.prob.n_qubits, r.prob.n_elec, r.D, r.precision};
       auto ci = srv->classes.find(key);
       if (ci == srv->classes.end()) {
-        try {
-          ci = srv->classes.emplace(key, make_class(srv, r)).first;
-        } catch (const OomError&) {
+        // a new class; when it does not fit the budget, idle classes (nothing
+        // queued for them, nothing running) give their memory back, least
+        // recently used first
+        std::unique_ptr<SrvClass> made;
+        while (!made) {
+          try {
+            made = make_class(srv, r);
+          } catch (const OomError&) {
+            auto victim = srv->classes.end();
+            for (auto vi = srv->classes.begin(); vi != srv->classes.end(); ++vi) {
+              const SrvClass& v = *vi->second;
+              if (v.in_flight || v.active() > 0 || class_queued(srv, vi->first)) continue;
+              if (victim == srv->classes.end() || v.last_use < victim->second->last_use) victim = vi;
+            }
+            if (victim == srv->classes.end()) break;
+            srv->classes.erase(victim);
+          }
+        }
+        if (!made) {
           ++it;  // waits until memory frees up
           continue;
         }
+        ci = srv->classes.emplace(key, std::move(made)).first;
       }
       SrvClass& c = *ci->second;
       const int slot = c.in_flight ? -1 : c.free_slot();
@@ -335,6 +361,7 @@ int q2c_server_step(q2c_server* srv, int* n_queued, int* n_active, int* n_ready)
         ++it;
         continue;
       }
+      c.last_use = srv->steps;
       std::unique_ptr<SrvRequest> req = std::move(*it);
       it = srv->queue.erase(it);
       try {
@@ -357,15 +384,12 @@ int q2c_server_step(q2c_server* srv, int* n_queued, int* n_active, int* n_ready)
                 "gates");
       hip_check(hipEventRecord(c.done, c.stream), "event");
       c.in_flight = true;
+      c.last_use = srv->steps;
     }
-    // classes with nothing queued or running give their memory back
-    for (auto it = srv->classes.begin(); it != srv->classes.end();) {
-      SrvClass& c = *it->second;
-      bool wanted = c.in_flight || c.active() > 0;
-      for (const auto& r : srv->queue)
-        wanted = wanted || (ClassKey{r->prob.n_qubits, r->prob.n_elec, r->D, r->precision} == it->first);
-      it = wanted ? std::next(it) : srv->classes.erase(it);
-    }
+    // idle classes keep their slots and compiled gate list for the next
+    // request of their shape; they are evicted only when a new class needs
+    // the memory (step 2)
+    ++srv->steps;
     int act = 0;
     for (auto& kv : srv->classes) act += kv.second->active();
     if (n_queued) *n_queued = int(srv->queue.size());

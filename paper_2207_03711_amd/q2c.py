@@ -199,6 +199,7 @@ _pu8 = C.POINTER(C.c_uint8)
 SIGNATURES = {
     "q2c_ctx_create": (C.c_int, [C.c_int, _vp, C.POINTER(q2c_opts), _pvp]),
     "q2c_ctx_destroy": (C.c_int, [_vp]),
+    "q2c_ctx_memory": (C.c_int, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "mps_create": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _pu8, _pvp]),
     "mps_destroy": (C.c_int, [_vp]),
     "mps_apply_gate": (C.c_int, [_vp, C.c_int, _pd, _pd]),
@@ -274,6 +275,13 @@ def q2c_ctx_create(device: int = 0, hip_stream: int | None = None, opts: q2c_opt
 
 def q2c_ctx_destroy(ctx) -> None:
     _check(lib.q2c_ctx_destroy(ctx))
+
+
+def q2c_ctx_memory(ctx):
+    """(bytes in use, budget) of a context."""
+    used, budget = C.c_size_t(), C.c_size_t()
+    _check(lib.q2c_ctx_memory(ctx, C.byref(used), C.byref(budget)))
+    return used.value, budget.value
 
 
 def mps_create(ctx, n_qubits: int, max_bond: int, precision: int, occ):

@@ -96,3 +96,58 @@ def test_server_rejects_bad_requests(q2c):
     assert srv.step() == (0, 0, 0)
     srv.close()
     ctx.close()
+
+
+def test_idle_classes_evicted_under_budget(q2c):
+    """Idle request classes stay allocated for later requests of their shape;
+    a new class that does not fit the context's HBM budget evicts idle
+    classes, least recently used first.  The peak memory of one class (4
+    qubits, D = 4) is measured; under a budget of 1.3 times that, requests of
+    D = 4, 3 and 2 served one after another all complete (the second needs
+    the first class evicted), within the budget, and each result equals the
+    same problem run alone."""
+    from workloads import ServingRequest
+
+    reqs = [ServingRequest(i, 1, D, 0.2, 0.0) for i, D in enumerate((4, 3, 2))]
+
+    def serve(ctx, srv, r, watch=None):
+        I = r.integrals()
+        srv.submit(r.index, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const, r.theta(), r.max_bond, q2c.Q2C_FP64,
+                   r.n_frag_orb)
+        t0 = time.time()
+        while True:
+            srv.step()
+            if watch is not None:
+                watch.append(q2c.q2c_ctx_memory(ctx.h)[0])
+            out = srv.poll()
+            if out:
+                return out[0]
+            assert time.time() - t0 < 60, "request never admitted"
+
+    ctx0 = q2c.Context(0)
+    srv0 = q2c.Server(ctx0, slots_per_class=2, gates_per_step=64)
+    base = q2c.q2c_ctx_memory(ctx0.h)[0]
+    seen = []
+    serve(ctx0, srv0, reqs[0], seen)
+    peak = max(seen) - base
+    srv0.close()
+    ctx0.close()
+    assert peak > 0
+
+    budget = base + int(1.3 * peak)
+    ctx = q2c.Context(0, hbm_budget_bytes=budget)
+    ctx_alone = q2c.Context(0)  # reference runs outside the budget
+    srv = q2c.Server(ctx, slots_per_class=2, gates_per_step=64)
+    used = []
+    for r in reqs:
+        res = serve(ctx, srv, r, used)
+        assert res["status"] == 0
+        I = r.integrals()
+        p = q2c.Problem(ctx_alone, I.n_orb, I.n_elec, I.h1, I.eri, I.e_const)
+        e_alone, _ = p.energy(r.theta(), r.max_bond)
+        p.close()
+        assert res["energy"] == e_alone, r.max_bond
+    assert max(used) <= budget
+    srv.close()
+    ctx.close()
+    ctx_alone.close()
