@@ -48,3 +48,11 @@ def test_gate_phase_split():
     s = bench.gate_phase_split(cyc)
     assert abs(s["contract"] - 0.06) < 1e-15 and abs(s["svd"] - 0.87) < 1e-15 and abs(s["update"] - 0.07) < 1e-15
     assert abs(sum(s["svd_parts"].values()) - s["svd"]) < 1e-15
+
+
+def test_traffic_constant_matches_kernel_source():
+    """The HBM traffic figure in the bench line belongs to one kernel source:
+    a kernel change must come with new counter passes (else the bench
+    reports null)."""
+    assert bench.measured_traffic("q16_d64") is not None
+    assert bench.measured_traffic("q8_d16") is None
