@@ -64,3 +64,18 @@ def test_degenerate_fermi_level_is_an_error():
     level: no unique mean-field determinant."""
     with pytest.raises(ValueError):
         dmet.mean_field_density(random_lattice(8, 2, 8, 1, eps_amp=0.0, ring=True))
+
+
+@pytest.mark.parametrize("k,solver", [(1, "fci"), (2, "fci"), (4, "fci"), (2, "uccsd")])
+def test_fragment_energies_add_up_to_the_mean_field_energy(k, solver):
+    """U = 0, mu = 0: the embedded ground state is the projected mean-field
+    determinant, so the fragment energies (democratic partitioning of the
+    one-body energy) add up to the mean-field energy 2 Tr(h D)."""
+    lat = random_lattice(8, k, 8, 5, U=0.0)
+    D = dmet.mean_field_density(lat)
+    total = 0.0
+    for f in range(lat.n_frags):
+        N = dmet.embedding_basis(lat, D, f)
+        _, ef, _ = dmet.solve_fragment(lat, dmet.embedded_problem(lat, N, f, 0.0), solver)
+        total += ef
+    assert abs(total - 2.0 * np.trace(lat.h @ D)) < 1e-12
