@@ -56,3 +56,15 @@ def test_traffic_constant_matches_kernel_source():
     reports null)."""
     assert bench.measured_traffic("q16_d64") is not None
     assert bench.measured_traffic("q8_d16") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU; asked for more it exits with status 2 and a
+    message, before touching a device."""
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
