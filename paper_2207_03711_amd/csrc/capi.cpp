@@ -87,6 +87,10 @@ struct vqe_problem {
   q2c::DevProblem dev;
   DBuf gsite, grot, gpre, gpost, rc, rparam, sx, sz, sc, sord, sshr, occ;
   std::map<std::tuple<int, int, int>, std::unique_ptr<Batch>> batches;  // (D, slots, precision)
+  // (D, precision): the one-slot batch of the unshifted circuit in forked
+  // parameter shifts, apart from `batches` so that a one-circuit batch of
+  // shifted circuits never shares its slot
+  std::map<std::tuple<int, int>, std::unique_ptr<Batch>> base_batches;
   DBuf theta, shift_rot, shift_val, ev_re, ev_im, energies, scratch, phi, cursor, pairs;
   size_t theta_cap = 0, srot_cap = 0, sval_cap = 0, evr_cap = 0, evi_cap = 0, en_cap = 0, scratch_cap = 0,
          phi_cap = 0, cursor_cap = 0, pairs_cap = 0;
@@ -110,6 +114,13 @@ Batch& batch_for(vqe_problem* p, int D, int n_slots, int precision) {
   if (!p->batches.count(key))
     p->batches[key] = std::make_unique<Batch>(p->ctx, p->host.n_qubits, D, n_slots, precision);
   return *p->batches[key];
+}
+
+Batch& base_batch_for(vqe_problem* p, int D, int precision) {
+  auto key = std::make_tuple(D, precision);
+  if (!p->base_batches.count(key))
+    p->base_batches[key] = std::make_unique<Batch>(p->ctx, p->host.n_qubits, D, 1, precision);
+  return *p->base_batches[key];
 }
 
 bool progress_enabled() {
@@ -1056,8 +1067,8 @@ void shift_energies_forked(vqe_problem* p, const double* theta, const std::vecto
     i0 = w.hi;
     win.push_back(std::move(w));
   }
-  // base slot: the unshifted circuit, on the second stream
-  Batch& base = batch_for(p, max_bond, 1, precision);
+  // base slot: the unshifted circuit, on the second stream, in a batch of its own
+  Batch& base = base_batch_for(p, max_bond, precision);
   SlotStore* store[2] = {&snap_store(p, max_bond, precision, W, 0), &snap_store(p, max_bond, precision, W, 1)};
   ensure(ctx, p->theta, p->theta_cap, sizeof(double) * size_t(std::max(1, C) * np));
   ensure(ctx, p->phi, p->phi_cap, sizeof(double) * size_t(C) * std::max(1, p->dev.n_rot));

@@ -202,3 +202,24 @@ def test_mixed_gradient_within_bar(q2c, rule):
         p_.close()
     for c in (cg, ce):
         c.close()
+
+
+@pytest.mark.parametrize("rule", [1, 0])
+def test_one_slot_windows_keep_the_base_slot_apart(q2c, rule):
+    """With one slot every batch of shifted circuits holds a single circuit,
+    the shape of the unshifted (base) circuit's own batch; the base slot must
+    not be shared with them.  Forked batch graphs and forked eager batches
+    equal eager from-start runs bit for bit (6 qubits, both rules)."""
+    I = random_integrals(3, 2, 4)
+    th = random_theta(n_uccsd_params(3, 2), 12, amp=0.3)
+    ctxs = [q2c.Context(0, slots=1, grad_rule=rule),
+            q2c.Context(0, slots=1, grad_rule=rule, eager_batches=1),
+            q2c.Context(0, slots=1, grad_rule=rule, shift_from_start=1, eager_batches=1)]
+    probs = [_problem(q2c, c, I) for c in ctxs]
+    out = [p_.grad(th, 8) for p_ in probs]
+    (gg, eg, _), (ge, ee, _), (gs, es, _) = out
+    assert np.array_equal(gg, gs) and np.array_equal(ge, gs) and eg == ee == es
+    for p_ in probs:
+        p_.close()
+    for c in ctxs:
+        c.close()
